@@ -1,0 +1,268 @@
+"""Seeded synthetic read-pair workloads.
+
+This module only draws random sequences. It holds none of the alignment
+arithmetic: it is shared by the oracle tests and the HIP path, and neither of
+them imports the other.
+
+The paper measures on Genome-in-a-Bottle HiFi/CLR/ONT reads mapped to GRCh38
+after Minimap2 seeding and chaining (Section 5.1); none of that data is
+available, so seeded synthetic pairs with the shapes of those workloads stand
+in for it. Every sequence is ASCII (``A C G T`` and ``N``), concatenated into
+one ``uint8`` buffer per side with ``int64`` start offsets and ``int32``
+lengths, so the same bytes feed the oracle and the device packer.
+
+Workload recipes (target = reference, query = mutated target):
+
+* ``cfg1``  500 pairs, target length U{100..1000}, 5% errors (subst:ins:del
+  2:1:1), no N; band 500, z-drop 400.
+* ``cfg2``  100k ONT-like pairs, target length clip(round(LogNormal(ln 2000,
+  0.8)), 1, 20000), 10% errors (1:1:1), then every base of both sequences
+  becomes N with probability 0.001; band 751, z-drop 400.
+* ``cfg3``  1M pairs, target length min(50000, floor(50 * U**(-1/1.5)))
+  (Pareto tail, alpha 1.5), 8% errors (1:1:1); 20% of the pairs get an
+  unrelated U{2000..5000} random segment inserted into the query at a uniform
+  position; band 751, z-drop 400.
+* ``cfg4``  20k HiFi-like pairs, target length U{10000..25000}, 1% errors
+  (1:1:1) plus U{1,2,3} long indels of U{50..500} bases each (insertion of
+  random bases or deletion, probability 1/2 each); band 2000, z-drop 5000.
+
+Point errors: each target base independently is an error with the stated
+rate; a substitution draws one of the three other bases uniformly, an
+insertion emits a random base after the original, a deletion drops the base.
+Every config is drawn from ``numpy.random.default_rng([config_id, seed])``.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+from typing import Optional, Sequence
+
+import numpy as np
+
+ALPHABET = np.frombuffer(b"ACGT", dtype=np.uint8)
+N_BYTE = ord("N")
+
+# Scoring shared by every workload: match +2, mismatch -4, gap pieces
+# (open 4, extend 2) and (open 24, extend 1), N scored -1.
+SCORING = dict(a=2, b=4, q=4, e=2, q2=24, e2=1, ambig=1)
+
+
+@dataclasses.dataclass
+class PairBatch:
+    """A batch of (target, query) pairs as concatenated ASCII buffers."""
+
+    t_seq: np.ndarray  # uint8, concatenated targets
+    t_off: np.ndarray  # int64, start of each target in t_seq
+    t_len: np.ndarray  # int32
+    q_seq: np.ndarray  # uint8, concatenated queries
+    q_off: np.ndarray  # int64
+    q_len: np.ndarray  # int32
+    scoring: dict
+    w: int
+    zdrop: int
+    name: str = "custom"
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.t_len.shape[0])
+
+    def target(self, p: int) -> bytes:
+        o = int(self.t_off[p])
+        return self.t_seq[o:o + int(self.t_len[p])].tobytes()
+
+    def query(self, p: int) -> bytes:
+        o = int(self.q_off[p])
+        return self.q_seq[o:o + int(self.q_len[p])].tobytes()
+
+    def subset(self, idx: Sequence[int]) -> "PairBatch":
+        """A new batch holding pairs ``idx`` (in that order), re-concatenated."""
+        idx = np.asarray(idx, dtype=np.int64)
+        ts = [self.target(int(p)) for p in idx]
+        qs = [self.query(int(p)) for p in idx]
+        return from_lists(ts, qs, self.scoring, self.w, self.zdrop,
+                          name=f"{self.name}[{len(idx)}]")
+
+    def digest(self) -> str:
+        h = hashlib.sha256()
+        for arr in (self.t_seq, self.t_off, self.t_len, self.q_seq, self.q_off, self.q_len):
+            h.update(np.ascontiguousarray(arr).tobytes())
+        return h.hexdigest()
+
+
+def from_lists(targets: Sequence[bytes], queries: Sequence[bytes], scoring: Optional[dict] = None,
+               w: int = -1, zdrop: int = -1, name: str = "custom") -> PairBatch:
+    """Build a batch from explicit byte strings (tests and examples)."""
+    if len(targets) != len(queries):
+        raise ValueError("targets and queries must have the same count")
+
+    def pack(seqs):
+        lens = np.array([len(s) for s in seqs], dtype=np.int32)
+        off = np.zeros(len(seqs), dtype=np.int64)
+        if len(seqs):
+            off[1:] = np.cumsum(lens[:-1], dtype=np.int64)
+        buf = np.frombuffer(b"".join(bytes(s) for s in seqs), dtype=np.uint8).copy()
+        return buf, off, lens
+
+    ts, to, tl = pack(targets)
+    qs, qo, ql = pack(queries)
+    return PairBatch(ts, to, tl, qs, qo, ql, dict(scoring or SCORING), int(w), int(zdrop), name)
+
+
+def _random_bases(rng: np.random.Generator, count: int) -> np.ndarray:
+    return ALPHABET[rng.integers(0, 4, size=count)]
+
+
+def _mutate(rng: np.random.Generator, seq: np.ndarray, lens: np.ndarray, rate: float,
+            ratio: Sequence[float]):
+    """Apply per-base point errors to concatenated ``seq`` (segments ``lens``)."""
+    L = seq.shape[0]
+    kind = np.zeros(L, dtype=np.int8)  # 0 keep, 1 subst, 2 ins, 3 del
+    err = rng.random(L) < rate
+    p = np.asarray(ratio, dtype=np.float64)
+    kind[err] = rng.choice(3, size=int(err.sum()), p=p / p.sum()).astype(np.int8) + 1
+    base = seq.copy()
+    sub = kind == 1
+    if sub.any():
+        code = np.searchsorted(ALPHABET, base[sub])
+        base[sub] = ALPHABET[(code + rng.integers(1, 4, size=int(sub.sum()))) % 4]
+    cnt = np.ones(L, dtype=np.int64)
+    cnt[kind == 3] = 0
+    cnt[kind == 2] = 2
+    out = np.repeat(base, cnt)
+    last = np.cumsum(cnt) - 1
+    ins = kind == 2
+    out[last[ins]] = _random_bases(rng, int(ins.sum()))
+    seg_start = np.zeros(len(lens), dtype=np.int64)
+    if len(lens):
+        seg_start[1:] = np.cumsum(lens[:-1], dtype=np.int64)
+    csum = np.concatenate([[0], np.cumsum(cnt)])
+    new_lens = (csum[seg_start + lens] - csum[seg_start]).astype(np.int64)
+    return out, new_lens
+
+
+def _offsets(lens: np.ndarray) -> np.ndarray:
+    off = np.zeros(len(lens), dtype=np.int64)
+    if len(lens):
+        off[1:] = np.cumsum(lens[:-1], dtype=np.int64)
+    return off
+
+
+def _splice(rng, q_seq, q_lens, which, seg_lo, seg_hi, mode):
+    """Insert random segments into (mode 'ins') or delete segments from
+    (mode 'del') the queries flagged in ``which``; one event per flag."""
+    q_off = _offsets(q_lens)
+    pieces = []
+    new_lens = q_lens.copy()
+    cursor = 0
+    for p in np.nonzero(which)[0]:
+        o, ln = int(q_off[p]), int(q_lens[p])
+        pieces.append(q_seq[cursor:o])
+        cur = q_seq[o:o + ln]
+        seg = int(rng.integers(seg_lo, seg_hi + 1))
+        if mode == "ins":
+            pos = int(rng.integers(0, ln + 1))
+            cur = np.concatenate([cur[:pos], _random_bases(rng, seg), cur[pos:]])
+        else:
+            seg = min(seg, max(ln - 1, 0))
+            pos = int(rng.integers(0, ln - seg + 1)) if ln - seg >= 0 else 0
+            cur = np.concatenate([cur[:pos], cur[pos + seg:]])
+        pieces.append(cur)
+        new_lens[p] = cur.shape[0]
+        cursor = o + ln
+    pieces.append(q_seq[cursor:])
+    return np.concatenate(pieces) if pieces else q_seq, new_lens
+
+
+def _sprinkle_n(rng, seq, rate):
+    if rate > 0:
+        hit = rng.random(seq.shape[0]) < rate
+        seq = seq.copy()
+        seq[hit] = N_BYTE
+    return seq
+
+
+def _finish(t_seq, t_lens, q_seq, q_lens, w, zdrop, name):
+    t_lens = np.asarray(t_lens, dtype=np.int32)
+    q_lens = np.asarray(q_lens, dtype=np.int32)
+    return PairBatch(np.ascontiguousarray(t_seq, dtype=np.uint8), _offsets(t_lens), t_lens,
+                     np.ascontiguousarray(q_seq, dtype=np.uint8), _offsets(q_lens), q_lens,
+                     dict(SCORING), int(w), int(zdrop), name)
+
+
+CONFIG_PAIRS = {1: 500, 2: 100_000, 3: 1_000_000, 4: 20_000}
+CONFIG_BAND = {1: (500, 400), 2: (751, 400), 3: (751, 400), 4: (2000, 5000)}
+
+
+def make_config(config_id: int, n_pairs: Optional[int] = None, seed: int = 0) -> PairBatch:
+    """Draw workload ``config_id`` (1..4). ``n_pairs`` truncates the draw to a
+    prefix-sized batch with the same distribution (a smaller sample)."""
+    if config_id not in CONFIG_PAIRS:
+        raise ValueError(f"unknown config {config_id}")
+    rng = np.random.default_rng([config_id, seed])
+    P = CONFIG_PAIRS[config_id] if n_pairs is None else int(n_pairs)
+    w, zdrop = CONFIG_BAND[config_id]
+    name = f"cfg{config_id}" + ("" if n_pairs is None else f"[{P}]")
+    if config_id == 1:
+        tl = rng.integers(100, 1001, size=P)
+        t = _random_bases(rng, int(tl.sum()))
+        q, ql = _mutate(rng, t, tl, 0.05, (2, 1, 1))
+        return _finish(t, tl, q, ql, w, zdrop, name)
+    if config_id == 2:
+        tl = np.clip(np.round(rng.lognormal(np.log(2000.0), 0.8, size=P)), 1, 20000).astype(np.int64)
+        t = _random_bases(rng, int(tl.sum()))
+        q, ql = _mutate(rng, t, tl, 0.10, (1, 1, 1))
+        t = _sprinkle_n(rng, t, 0.001)
+        q = _sprinkle_n(rng, q, 0.001)
+        return _finish(t, tl, q, ql, w, zdrop, name)
+    if config_id == 3:
+        u = rng.random(P)
+        u = np.maximum(u, np.finfo(np.float64).tiny)
+        tl = np.minimum(50000, np.floor(50.0 * u ** (-1.0 / 1.5))).astype(np.int64)
+        t = _random_bases(rng, int(tl.sum()))
+        q, ql = _mutate(rng, t, tl, 0.08, (1, 1, 1))
+        which = rng.random(P) < 0.20
+        q, ql = _splice(rng, q, ql, which, 2000, 5000, "ins")
+        return _finish(t, tl, q, ql, w, zdrop, name)
+    # config 4
+    tl = rng.integers(10000, 25001, size=P)
+    t = _random_bases(rng, int(tl.sum()))
+    q, ql = _mutate(rng, t, tl, 0.01, (1, 1, 1))
+    n_events = rng.integers(1, 4, size=P)
+    for k in range(3):
+        which = n_events > k
+        is_ins = rng.random(P) < 0.5
+        q, ql = _splice(rng, q, ql, which & is_ins, 50, 500, "ins")
+        q, ql = _splice(rng, q, ql, which & ~is_ins, 50, 500, "del")
+    return _finish(t, tl, q, ql, w, zdrop, name)
+
+
+def random_pairs(rng: np.random.Generator, n_pairs: int, len_lo: int, len_hi: int,
+                 err: float = 0.1, ratio=(1, 1, 1), n_rate: float = 0.0,
+                 related: float = 1.0, scoring: Optional[dict] = None, w: int = -1,
+                 zdrop: int = -1, name: str = "random") -> PairBatch:
+    """Small random batches for tests: target lengths U{len_lo..len_hi};
+    a fraction ``related`` of queries are mutated targets, the rest are drawn
+    independently with the same length distribution."""
+    tl = rng.integers(len_lo, len_hi + 1, size=n_pairs)
+    t = _random_bases(rng, int(tl.sum()))
+    q, ql = _mutate(rng, t, tl, err, ratio)
+    unrelated = rng.random(n_pairs) >= related
+    if unrelated.any():
+        q_off = _offsets(ql)
+        pieces, lens = [], ql.copy()
+        for p in range(n_pairs):
+            if unrelated[p]:
+                ln = int(rng.integers(len_lo, len_hi + 1))
+                pieces.append(_random_bases(rng, ln))
+                lens[p] = ln
+            else:
+                pieces.append(q[q_off[p]:q_off[p] + ql[p]])
+        q = np.concatenate(pieces) if pieces else q
+        ql = lens
+    t = _sprinkle_n(rng, t, n_rate)
+    q = _sprinkle_n(rng, q, n_rate)
+    b = _finish(t, tl, q, ql, w, zdrop, name)
+    if scoring is not None:
+        b.scoring = dict(scoring)
+    return b
