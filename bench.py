@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X guided extension aligner.
+
+Workload: the ONT-like batch -- 100,000 seeded synthetic pairs, target length
+clip(round(LogNormal(ln 2000, 0.8)), 1, 20000), query = target with 10%
+errors (subst:ins:del 1:1:1), 0.1% N bases scored -1, scoring a=2 b=4 q=4 e=2
+q2=24 e2=1, band w=751, z-drop Z=400. The real long-read datasets the paper
+measures on (GIAB reads after Minimap2 seeding) are not available; these
+pairs stand in for them.
+
+One step = one ga_align_batch call over the whole batch: base unpacking,
+pair planning and the anti-diagonal sweep with z-drop for every pair. Inputs
+are packed and resident in HBM before the timed region starts.
+
+Prints one JSON line: GCUPS = algorithmic in-band cells up to each pair's
+termination anti-diagonal, per second.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+OPS_PER_CELL = 16           # int32 VALU lane-ops per cell (the roofline convention)
+PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # int32 lane-ops/s: CUs x SIMDs x lanes x clock
+DOMINANT_KERNEL_SRC = os.path.join(ROOT, "paper_2403_06478_amd", "csrc", "ga_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "ga_dp_kernel_k24_cfg2_pmc.md")
+
+
+def log(msg: str):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def kernel_source_hash() -> str:
+    with open(DOMINANT_KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(cls_name: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
+    if there is none or the kernel source changed since it was taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    return float(m.group(1)) if m else None
+
+
+def cpu_baseline(batch, n_sample: int):
+    import numpy as np
+
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    sub = batch.subset(np.arange(min(n_sample, batch.n_pairs)))
+    log(f"cpu baseline: oracle on {sub.n_pairs} pairs, {cores} threads")
+    t0 = time.perf_counter()
+    _, cells = oracle.align_batch(sub, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": round(float(cells.sum()) / dt / 1e9, 4), "unit": "GCUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {sub.n_pairs} pairs of the 100k-pair ONT-like draw "
+                      f"({int(cells.sum())} cells, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pairs", type=int, default=None, help="fewer pairs (profiling runs only)")
+    ap.add_argument("--cpu-sample", type=int, default=1200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): pairs are "
+              f"independent and would be split across GPUs with no exchange; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2403_06478_amd as ga
+    import seqgen
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    log("generating the ONT-like workload (100k pairs, seed 0)")
+    batch = seqgen.make_config(2, n_pairs=args.pairs)
+    ctx = ga.Context(0)
+    packed = ga.pack_batch(ctx, batch)
+    out = torch.empty((batch.n_pairs, 7), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    ctx.check()
+    stream = torch.cuda.current_stream()
+    log(f"packed {batch.n_pairs} pairs, {int(batch.t_len.sum() + batch.q_len.sum())} bases; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ga.ga_align_batch(ctx, packed, batch.scoring, batch.w, batch.zdrop, out=out, stream=stream)
+    torch.cuda.synchronize()
+    ctx.check()
+
+    ctx.set_timing(True)
+    stage_ms = []
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ga.ga_align_batch(ctx, packed, batch.scoring, batch.w, batch.zdrop, out=out, stream=stream)
+        stage_ms.append(ctx.timing())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    ctx.check()
+    elapsed = t1 - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    log(f"{ms_per_step:.2f} ms per step")
+
+    res = out.cpu().numpy()
+    t_len, q_len = batch.t_len, batch.q_len
+    cells = ga.count_cells(t_len, q_len, batch.w, res)
+    cls = np.array([ga.ga_pair_class(int(n), int(m), batch.w) for n, m in zip(t_len, q_len)])
+    total_cells = int(cells.sum())
+    gcups = total_cells / (ms_per_step / 1e3) / 1e9
+    pairs_per_s = batch.n_pairs / (ms_per_step / 1e3)
+
+    stage = np.array(stage_ms)  # [steps, 5]
+    mean_ms = stage.mean(axis=0)
+    dom = int(np.argmax(mean_ms[1:]))
+    dom_cells = int(cells[cls == dom].sum())
+    achieved = OPS_PER_CELL * dom_cells / (mean_ms[1 + dom] / 1e3) / 1e12
+    traffic = read_traffic(f"k{ga.CLASS_SLOTS[dom]}")
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / PEAK_TOPS, 4), "traffic": traffic,
+                "kernel": f"ga_dp_kernel<{ga.CLASS_SLOTS[dom]}>",
+                "kernel_ms": round(float(mean_ms[1 + dom]), 3),
+                "kernel_cells": dom_cells, "ops_per_cell": OPS_PER_CELL}
+    log(f"stages ms (prep, K8, K16, K24, K32): {[round(float(x), 3) for x in mean_ms]}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batch, args.cpu_sample)
+
+    line = {
+        "metric": "GCUPS",
+        "value": round(gcups, 3),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "ONT-like batch: 100k pairs, target LogNormal(median 2 kb, sigma 0.8) "
+                               "capped at 20 kb, 10% errors 1:1:1, 0.1% N scored -1, "
+                               "a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, seed 0",
+                   "pairs": batch.n_pairs, "w": batch.w, "Z": batch.zdrop,
+                   "cells": total_cells, "zdropped": int(res[:, 6].sum())},
+        "pairs_per_s": round(pairs_per_s, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,147 @@
+/*
+ * ga.h -- C ABI of the MI355X guided extension aligner.
+ *
+ * The library computes, for a batch of (target, query) pairs, the banded
+ * two-piece affine-gap extension alignment with per-anti-diagonal maximum
+ * tracking and z-drop termination of AGAThA (PPoPP'24, arXiv 2403.06478),
+ * Section 2.1: the score table of Eq. 1-3 (generalised to two gap pieces)
+ * restricted to a diagonal band (k-banding), and the termination condition
+ * of Eq. 4-7. Every result is exact int32.
+ *
+ * Definition (0-based; i indexes the target T, j the query Q):
+ *   S(x,y) = -ambig if x or y is N, +a if x == y, else -b.
+ *   A gap run of length l costs min(q + l*e, q2 + l*e2).
+ *   Lattice point (i,j), i,j >= -1, is usable iff w < 0 or |i-j| <= w.
+ *   H(i,j) = best score of an alignment path from (-1,-1) to (i,j) through
+ *            usable points, each maximal gap run charged as above.
+ *   Anti-diagonal r = i+j, r = 0..n+m-2: M_r = max H over its in-band cells,
+ *   (mi,mj) the cell with the smallest i attaining it. Starting from
+ *   G = 0 at (-1,-1): if M_r > G the maximum moves to (M_r,mi,mj); else if
+ *   Z >= 0, mi > gi, mj > gj and G - M_r > Z + e2*|(mi-gi)-(mj-gj)| the pair
+ *   is z-dropped at r and the sweep stops. end_* is (M_r,mi,mj) of the last
+ *   anti-diagonal examined. Empty sequences give (0,-1,-1,0,-1,-1,0).
+ *
+ * Conventions: every pointer named *_dev is device memory owned by the
+ * caller; the library never frees caller memory. Calls returning an int give
+ * GA_OK (0) or a negative GA_E* code; validation happens on the host before
+ * any launch. Work is enqueued on `stream` (a hipStream_t, NULL = default
+ * stream) and is asynchronous: results are valid once the stream has
+ * completed. Errors found on the device (a pair longer than the declared
+ * bound, offsets outside the packed streams) are latched in the context and
+ * reported by ga_context_check().
+ */
+#ifndef GA_H
+#define GA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GA_OK 0
+#define GA_EINVAL (-1)       /* null pointer, negative size or parameter, range guard */
+#define GA_ENOMEM (-2)       /* device workspace allocation failed */
+#define GA_EHIP (-3)         /* HIP launch or runtime error */
+#define GA_EUNSUPPORTED (-4) /* parameters outside what the kernels implement */
+#define GA_EDEVICE (-5)      /* a device-side check failed (see ga_context_check) */
+
+/* Scoring (Section 2.1): match +a, mismatch -b, N against anything -ambig,
+ * gap run of length l costs min(q + l*e, q2 + l*e2). Every field >= 0.
+ * The kernels take a <= 127, b <= 128, ambig <= 128 (8-bit score table). */
+typedef struct {
+    int32_t a, b, q, e, q2, e2, ambig;
+} ga_scoring_t;
+
+/* Per-pair result, 28 bytes, 0-based indices; -1 means "the origin". */
+typedef struct {
+    int32_t max_score, max_i, max_j; /* global maximum G and its cell */
+    int32_t end_score, end_i, end_j; /* anti-diagonal maximum where the sweep ended */
+    int32_t zdropped;                /* 1 if the z-drop condition fired */
+} ga_result_t;
+
+/* A packed batch (input packing, Section 2.2): bases as 2-bit codes A=0 C=1
+ * G=2 T=3, 16 per uint32; base k of a sequence starting at word `off` sits at
+ * bits 2*(k%16) of word off + k/16. The optional N bitmap holds one bit per
+ * base position of the 2-bit stream: base k of that sequence is N iff bit
+ * (16*off + k) % 32 of word (16*off + k) / 32 is set; NULL means no N. */
+typedef struct {
+    int64_t n_pairs;
+    const uint32_t *t_words_dev; /* target 2-bit stream */
+    int64_t t_nwords;            /* its length in words */
+    const uint32_t *q_words_dev; /* query 2-bit stream */
+    int64_t q_nwords;
+    const int64_t *t_off_dev;    /* [n_pairs] first word of each target */
+    const int64_t *q_off_dev;    /* [n_pairs] first word of each query */
+    const int32_t *t_len_dev;    /* [n_pairs] target lengths in bases */
+    const int32_t *q_len_dev;    /* [n_pairs] query lengths in bases */
+    const uint32_t *t_nmask_dev; /* N bitmap of the target stream, or NULL */
+    const uint32_t *q_nmask_dev; /* N bitmap of the query stream, or NULL */
+    int32_t max_len;             /* caller's bound on every t_len and q_len */
+} ga_batch_t;
+
+typedef struct ga_context ga_context_t;
+
+/* Create a context on HIP device `device`; it owns the device workspace
+ * (unpacked bases, work lists, counters). Returns GA_EINVAL for a bad device. */
+int ga_context_create(ga_context_t **ctx, int device);
+
+/* Release the context and its workspace (synchronises the device). */
+int ga_context_destroy(ga_context_t *ctx);
+
+/* Wait for `stream`, then report and clear the device-side error latch:
+ * GA_OK, or GA_EDEVICE if any pair violated the batch's declared bounds
+ * (such pairs get the result {0,-1,-1,0,-1,-1,-1}). */
+int ga_context_check(ga_context_t *ctx, void *stream);
+
+/* Human-readable text for a GA_* code (static storage). */
+const char *ga_strerror(int code);
+
+/* Number of uint32 words ga_pack writes for sequences of the given lengths
+ * (host array), i.e. the sum of ceil(len/16). */
+int64_t ga_pack_words(const int32_t *len_host, int64_t n);
+
+/* On-device input packing (Section 2.2, input packing): `ascii_dev` holds
+ * n sequences, sequence p at byte offset off_dev[p] with length len_dev[p].
+ * Writes word_off_dev[p] (exclusive prefix sum of ceil(len/16)), the 2-bit
+ * stream words_dev[0 .. ga_pack_words) and the N bitmap
+ * nmask_dev[0 .. (ga_pack_words+1)/2). Any byte outside ACGTacgt becomes N
+ * (2-bit code 0 plus its N bit). `nwords` must equal ga_pack_words(len). */
+int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
+            const int32_t *len_dev, int64_t n, int64_t nwords, uint32_t *words_dev,
+            int64_t *word_off_dev, uint32_t *nmask_dev, void *stream);
+
+/* Align every pair of `batch` (Section 2.1, Eq. 1-7) with band half-width w
+ * (w < 0: no band) and z-drop threshold Z (Z < 0: never drop), writing
+ * out_dev[p] for each pair. Range guard (GA_EINVAL otherwise):
+ * (2*max_len + 2) * (max(a, b, ambig, q+e, q2+e2) + a + e2) + max(Z,0) < 2^29.
+ * Band widths with 2*min(w, max_len) + 1 > 2048 return GA_EUNSUPPORTED. */
+int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
+                   int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);
+
+/* Stage timing for benchmarking: while enabled, ga_align_batch records HIP
+ * events on its stream around its stages. */
+int ga_context_set_timing(ga_context_t *ctx, int enable);
+
+/* Milliseconds spent by the stages of the last timed ga_align_batch on this
+ * context (waits for those events): ms[0] = unpack + planning kernels,
+ * ms[1+c] = the alignment kernel of slot class c (K = 8, 16, 24, 32 slots
+ * per lane), for c < n-1. GA_EINVAL if timing was off for that call. */
+int ga_context_timing(ga_context_t *ctx, float *ms, int n);
+
+/* Slot class (0..3) that ga_align_batch uses for a pair of lengths n, m at
+ * band w, or -1 for an empty pair or a band wider than the kernels hold.
+ * Host function, for attributing work to the per-class kernels. */
+int ga_pair_class(int32_t n, int32_t m, int32_t w);
+
+/* Algorithmic work of one pair: the number of in-band cells (i,j),
+ * 0 <= i < n, 0 <= j < m, on anti-diagonals 0..r_end (r_end = end_i+end_j);
+ * 0 when n or m is 0. Host function: sums the band's cell count of each
+ * anti-diagonal, which is an interval of rows with closed-form ends. */
+int64_t ga_count_cells(int32_t n, int32_t m, int32_t w, int32_t r_end);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GA_H */

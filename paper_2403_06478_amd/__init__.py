@@ -1,0 +1,260 @@
+"""Python binding of the MI355X guided extension aligner (``libga.so``).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+kernels behind the C ABI of ``include/ga.h`` (same function names). PyTorch
+provides device memory and streams. There is no CPU fallback: if the HIP
+library is missing or no GPU is present the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libga.so")
+
+GA_OK = 0
+GA_EINVAL = -1
+GA_ENOMEM = -2
+GA_EHIP = -3
+GA_EUNSUPPORTED = -4
+GA_EDEVICE = -5
+
+RESULT_FIELDS = ("max_score", "max_i", "max_j", "end_score", "end_i", "end_j", "zdropped")
+
+# Exported symbols of libga.so, as declared in include/ga.h.
+ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "ga_strerror",
+               "ga_pack_words", "ga_pack", "ga_align_batch", "ga_count_cells",
+               "ga_context_set_timing", "ga_context_timing", "ga_pair_class")
+
+# Slot counts per lane of the alignment kernels, by class.
+CLASS_SLOTS = (8, 16, 24, 32)
+
+
+class GaError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("a", "b", "q", "e", "q2", "e2", "ambig")]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("n_pairs", ctypes.c_int64),
+        ("t_words_dev", ctypes.c_void_p), ("t_nwords", ctypes.c_int64),
+        ("q_words_dev", ctypes.c_void_p), ("q_nwords", ctypes.c_int64),
+        ("t_off_dev", ctypes.c_void_p), ("q_off_dev", ctypes.c_void_p),
+        ("t_len_dev", ctypes.c_void_p), ("q_len_dev", ctypes.c_void_p),
+        ("t_nmask_dev", ctypes.c_void_p), ("q_nmask_dev", ctypes.c_void_p),
+        ("max_len", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load ``libga.so`` (built in-tree by ``build.build()``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.ga_context_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.ga_context_create.restype = ctypes.c_int
+    lib.ga_context_destroy.argtypes = [vp]
+    lib.ga_context_destroy.restype = ctypes.c_int
+    lib.ga_context_check.argtypes = [vp, vp]
+    lib.ga_context_check.restype = ctypes.c_int
+    lib.ga_strerror.argtypes = [ctypes.c_int]
+    lib.ga_strerror.restype = ctypes.c_char_p
+    lib.ga_pack_words.argtypes = [vp, i64]
+    lib.ga_pack_words.restype = i64
+    lib.ga_pack.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
+    lib.ga_pack.restype = ctypes.c_int
+    lib.ga_align_batch.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), i32, i32, vp, vp]
+    lib.ga_align_batch.restype = ctypes.c_int
+    lib.ga_count_cells.argtypes = [i32, i32, i32, i32]
+    lib.ga_count_cells.restype = i64
+    lib.ga_context_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.ga_context_set_timing.restype = ctypes.c_int
+    lib.ga_context_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    lib.ga_context_timing.restype = ctypes.c_int
+    lib.ga_pair_class.argtypes = [i32, i32, i32]
+    lib.ga_pair_class.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().ga_strerror(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != GA_OK:
+        raise GaError(code, what)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device available: the aligner runs only on the GPU")
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def scoring_struct(sc: dict) -> Scoring:
+    return Scoring(*(int(sc[k]) for k in ("a", "b", "q", "e", "q2", "e2", "ambig")))
+
+
+class Context:
+    """Owns a ``ga_context_t`` (device workspace) on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib.ga_context_create(ctypes.byref(h), self.device), "ga_context_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, stream=None):
+        _check(load_library().ga_context_check(self._h, _stream_handle(stream)), "ga_context_check")
+
+    def set_timing(self, enable: bool):
+        _check(load_library().ga_context_set_timing(self._h, 1 if enable else 0), "ga_context_set_timing")
+
+    def timing(self):
+        """Stage milliseconds of the last timed call: [prep, class0..class3]."""
+        ms = (ctypes.c_float * 5)()
+        _check(load_library().ga_context_timing(self._h, ms, 5), "ga_context_timing")
+        return [float(x) for x in ms]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().ga_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class PackedBatch:
+    """Device-resident packed pairs (2-bit streams, N bitmaps, offsets)."""
+
+    n_pairs: int
+    t_words: "object"
+    t_off: "object"
+    t_len: "object"
+    t_nmask: "object"
+    q_words: "object"
+    q_off: "object"
+    q_len: "object"
+    q_nmask: "object"
+    max_len: int
+
+    def struct(self) -> Batch:
+        b = Batch()
+        b.n_pairs = self.n_pairs
+        b.t_words_dev = self.t_words.data_ptr()
+        b.t_nwords = self.t_words.numel()
+        b.q_words_dev = self.q_words.data_ptr()
+        b.q_nwords = self.q_words.numel()
+        b.t_off_dev = self.t_off.data_ptr()
+        b.q_off_dev = self.q_off.data_ptr()
+        b.t_len_dev = self.t_len.data_ptr()
+        b.q_len_dev = self.q_len.data_ptr()
+        b.t_nmask_dev = self.t_nmask.data_ptr() if self.t_nmask is not None else None
+        b.q_nmask_dev = self.q_nmask.data_ptr() if self.q_nmask is not None else None
+        b.max_len = self.max_len
+        return b
+
+
+def _upload(torch, arr, dtype, device):
+    arr = np.ascontiguousarray(arr)
+    if arr.size == 0:
+        arr = np.zeros(1, dtype=arr.dtype)
+    return torch.from_numpy(arr).to(device=device, dtype=dtype)
+
+
+def ga_pack(ctx: Context, ascii_seq, off, lens, stream=None):
+    """Pack one side (targets or queries) on the device: ASCII bytes ->
+    (words, word offsets, N bitmap, lengths) as device tensors."""
+    torch = _torch()
+    lib = load_library()
+    dev = torch.device("cuda", ctx.device)
+    lens = np.ascontiguousarray(lens, dtype=np.int32)
+    n = int(lens.shape[0])
+    nwords = int(lib.ga_pack_words(lens.ctypes.data, n)) if n else 0
+    d_ascii = _upload(torch, np.asarray(ascii_seq, dtype=np.uint8), torch.uint8, dev)
+    d_off = _upload(torch, np.asarray(off, dtype=np.int64), torch.int64, dev)
+    d_len = _upload(torch, lens, torch.int32, dev)
+    words = torch.empty(max(nwords, 1), dtype=torch.int32, device=dev)
+    word_off = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    nmask = torch.empty(max((nwords + 1) // 2, 1), dtype=torch.int32, device=dev)
+    _check(lib.ga_pack(ctx.handle, d_ascii.data_ptr(), d_off.data_ptr(), d_len.data_ptr(), n, nwords,
+                       words.data_ptr(), word_off.data_ptr(), nmask.data_ptr(), _stream_handle(stream)),
+           "ga_pack")
+    return words[:max(nwords, 1)], word_off, nmask, d_len, nwords
+
+
+def pack_batch(ctx: Context, batch, stream=None) -> PackedBatch:
+    """Pack a ``seqgen.PairBatch`` (host ASCII) into device streams."""
+    tw, to, tm, tl, tn = ga_pack(ctx, batch.t_seq, batch.t_off, batch.t_len, stream)
+    qw, qo, qm, ql, qn = ga_pack(ctx, batch.q_seq, batch.q_off, batch.q_len, stream)
+    max_len = int(max(batch.t_len.max(initial=0), batch.q_len.max(initial=0)))
+    return PackedBatch(batch.n_pairs, tw[:max(tn, 1)], to, tl, tm, qw[:max(qn, 1)], qo, ql, qm, max_len)
+
+
+def ga_align_batch(ctx: Context, packed: PackedBatch, scoring: dict, w: int, Z: int,
+                   out=None, stream=None):
+    """Align every pair; returns (or fills) a device int32 tensor [n_pairs, 7]."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty((max(packed.n_pairs, 1), 7), dtype=torch.int32,
+                          device=torch.device("cuda", ctx.device))
+    b = packed.struct()
+    sc = scoring_struct(scoring)
+    _check(lib.ga_align_batch(ctx.handle, ctypes.byref(b), ctypes.byref(sc), int(w), int(Z),
+                              out.data_ptr(), _stream_handle(stream)), "ga_align_batch")
+    return out[:packed.n_pairs]
+
+
+def ga_pair_class(n: int, m: int, w: int) -> int:
+    return int(load_library().ga_pair_class(int(n), int(m), int(w)))
+
+
+def ga_count_cells(n: int, m: int, w: int, r_end: int) -> int:
+    return int(load_library().ga_count_cells(int(n), int(m), int(w), int(r_end)))
+
+
+def count_cells(t_len, q_len, w: int, results) -> np.ndarray:
+    """Algorithmic cells per pair from the results (closed form per pair)."""
+    res = np.asarray(results)
+    r_end = res[:, 4].astype(np.int64) + res[:, 5].astype(np.int64)
+    return np.array([ga_count_cells(int(n), int(m), w, int(r)) for n, m, r in zip(t_len, q_len, r_end)],
+                    dtype=np.int64)

@@ -1,0 +1,855 @@
+// ga_kernels.hip -- MI355X (gfx950) guided extension aligner: device code and
+// the C ABI declared in include/ga.h.
+//
+// Method: AGAThA (PPoPP'24, arXiv 2403.06478), Section 2.1 -- banded
+// two-piece affine-gap score table (Eq. 1-3) with per-anti-diagonal maximum
+// tracking and the z-drop termination test (Eq. 4-7).
+//
+// Kernel shape (differs from the paper's chunked row sweep, Sections 4.1-4.2):
+// one wave64 per pair sweeps the band anti-diagonal by anti-diagonal. Lane l
+// owns K consecutive diagonals d = i - j of the band (slots), kept entirely in
+// VGPRs. Cells of anti-diagonal r lie on diagonals d == r (mod 2), so a step
+// updates one parity class of slots from the other class, which holds
+// anti-diagonal r-1; the slot's own previous value is anti-diagonal r-2 (the
+// diagonal predecessor). Within a lane the up/left neighbours are the adjacent
+// slots; at lane edges they arrive by DPP wave_shr:1 / wave_shl:1. Every step
+// completes a whole anti-diagonal, so the local maximum of Eq. 6 is one wave
+// reduction and the z-drop test of Eq. 5 runs in order with no run-ahead: the
+// rolling window of partial maxima (Section 4.1) and the slice boundary
+// (Section 4.2) are not needed.
+//
+// Boundary cells (row -1 and column -1) are produced by the same recurrence:
+// the slots outside the rectangle start at -inf and the origin at 0, so the
+// first cells reached on each diagonal are exactly the boundary gap scores.
+// The band edges are walls of -inf: the left wall is the DPP fill value of
+// lane 0, the right wall is a slot forced to -inf after each update.
+//
+// Bases are unpacked once per batch from the 2-bit stream (plus N bitmap) to
+// one byte per base (0..3, N = 4). Per 8-step block each slot builds the
+// substitution scores of its next 4 cells with one v_perm_b32 table lookup
+// (4 signed bytes), and each cell extracts its byte with v_bfe_i32.
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "ga.h"
+
+namespace {
+
+constexpr int NEG = -(1 << 30);      // -inf sentinel; range guard keeps it apart
+constexpr int NEG_MAX = -(1 << 30) - (1 << 29);  // below every reachable value
+constexpr int PADB = 64;             // guard bytes around the unpacked streams
+constexpr int NCLASS = 4;            // slot counts K = 8, 16, 24, 32 per lane
+constexpr int WAVE = 64;
+
+// Device counters (per call): [0..4) class list sizes, [4..8) class heads.
+constexpr int CNT_COUNT = 0;
+constexpr int CNT_HEAD = 4;
+constexpr int CNT_WORDS = 16;
+
+struct DpArgs {
+    const uint8_t *tb;   // unpacked target bytes; tb[16*off + k] is base k
+    const uint8_t *qb;   // unpacked query bytes
+    const int64_t *t_off;
+    const int64_t *q_off;
+    const int32_t *t_len;
+    const int32_t *q_len;
+    const int32_t *list;  // this class's pair list
+    int32_t *counters;
+    ga_result_t *out;
+    int32_t cls;
+    int32_t w, Z;
+    int32_t oe1, oe2, e1, e2;
+    uint32_t lut_lo, lut_hi;  // substitution score per class byte (signed bytes)
+};
+
+__device__ __forceinline__ int dpp_from_lower_lane(int fill, int v) {
+    // lane l receives lane l-1's v; lane 0 receives `fill` (wave_shr:1)
+    return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ int dpp_from_upper_lane(int fill, int v) {
+    // lane l receives lane l+1's v; lane 63 receives `fill` (wave_shl:1)
+    return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
+}
+
+// Max over the 64 lanes, returned as a wave-uniform value.
+__device__ __forceinline__ int wave_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));   // quad_perm 2,3,0,1
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));  // row_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ uint32_t window4(const uint32_t *W, int o) {
+    // bytes o..o+3 of the little-endian byte array held in W (o compile-time)
+    return (o & 3) ? __builtin_amdgcn_alignbyte(W[(o >> 2) + 1], W[o >> 2], (uint32_t)(o & 3))
+                   : W[o >> 2];
+}
+
+template <int K>
+struct PairState {
+    int H[K], E1[K], E2[K], F1[K], F2[K];
+    uint32_t S4[K];  // packed scores of the slot's next 4 cells
+};
+
+// Update the slots of parity class C for cell index `kc` (0..3) of the block.
+template <int K, int C, int KC>
+__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &A) {
+    int hl_e = 0, e1_e = 0, e2_e = 0;  // left-edge inputs (class 0)
+    int hr_e = 0, f1_e = 0, f2_e = 0;  // right-edge inputs (class 1)
+    if (C == 0) {
+        hl_e = dpp_from_lower_lane(NEG, st.H[K - 1]);
+        e1_e = dpp_from_lower_lane(NEG, st.E1[K - 1]);
+        e2_e = dpp_from_lower_lane(NEG, st.E2[K - 1]);
+    } else {
+        hr_e = dpp_from_upper_lane(NEG, st.H[0]);
+        f1_e = dpp_from_upper_lane(NEG, st.F1[0]);
+        f2_e = dpp_from_upper_lane(NEG, st.F2[0]);
+    }
+#pragma unroll
+    for (int s = C; s < K; s += 2) {
+        const int hu = (s == 0) ? hl_e : st.H[s - 1];
+        const int e1u = (s == 0) ? e1_e : st.E1[s - 1];
+        const int e2u = (s == 0) ? e2_e : st.E2[s - 1];
+        const int hf = (s == K - 1) ? hr_e : st.H[s + 1];
+        const int f1l = (s == K - 1) ? f1_e : st.F1[s + 1];
+        const int f2l = (s == K - 1) ? f2_e : st.F2[s + 1];
+        const int ne1 = max(hu - A.oe1, e1u - A.e1);
+        const int ne2 = max(hu - A.oe2, e2u - A.e2);
+        const int nf1 = max(hf - A.oe1, f1l - A.e1);
+        const int nf2 = max(hf - A.oe2, f2l - A.e2);
+        const int sc = __builtin_amdgcn_sbfe((int)st.S4[s], 8 * KC, 8);
+        const int h = max(max(st.H[s] + sc, max(ne1, ne2)), max(nf1, nf2));
+        st.H[s] = h;
+        st.E1[s] = ne1;
+        st.E2[s] = ne2;
+        st.F1[s] = nf1;
+        st.F2[s] = nf2;
+    }
+}
+
+template <int K, int C>
+__device__ __forceinline__ void clamp_wall(PairState<K> &st, bool wall_lane, int wall_pos) {
+#pragma unroll
+    for (int s = C; s < K; s += 2) {
+        if (s == wall_pos) {
+            if (wall_lane) {
+                st.H[s] = NEG;
+                st.E1[s] = NEG;
+                st.E2[s] = NEG;
+                st.F1[s] = NEG;
+                st.F2[s] = NEG;
+            }
+        }
+    }
+}
+
+// Geometry of one pair (all wave-uniform).
+struct Geo {
+    int n, m;
+    int a0;        // lowest diagonal held (band edge, or -m: boundary row)
+    int dlo, dhi;  // interior diagonals
+    int r_last;    // last non-empty anti-diagonal
+    int D;         // number of diagonals held
+    int fast_lo, fast_hi;  // anti-diagonals where every held slot is interior
+    bool fast_ok;
+};
+
+template <int K, int C, bool MASKED>
+__device__ __forceinline__ int lane_max(const PairState<K> &st, int slo, int shi) {
+    int lm = NEG_MAX;
+#pragma unroll
+    for (int s = C; s < K; s += 2) {
+        if (MASKED) {
+            lm = (s >= slo && s <= shi) ? max(lm, st.H[s]) : lm;
+        } else {
+            lm = max(lm, st.H[s]);
+        }
+    }
+    return lm;
+}
+
+struct Track {
+    int G, gi, gj;
+    int endS, endI, endJ;
+    int zd;
+};
+
+// After the class-C update of anti-diagonal r: local maximum (Eq. 6),
+// global maximum (Eq. 7) and z-drop test (Eq. 5). Returns true when done.
+template <int K, int C, bool MASKED>
+__device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &A, const Geo &g,
+                                          Track &tr, int r, int lane) {
+    // interior diagonals of anti-diagonal r, clipped to its parity
+    int vlo = max(g.dlo, max(-r, r - 2 * g.m + 2));
+    int vhi = min(g.dhi, min(r, 2 * g.n - 2 - r));
+    vlo += (vlo - r) & 1;
+    vhi -= (vhi - r) & 1;
+    if (vlo > vhi) return r >= g.r_last;  // empty anti-diagonal: nothing to test
+    const int d0 = g.a0 + lane * K;
+    const int lm = lane_max<K, C, MASKED>(st, vlo - d0, vhi - d0);
+    const int M = wave_max(lm);
+    const bool need = (M > tr.G) || (A.Z >= 0 && tr.G - M > A.Z) || (r >= g.r_last);
+    if (need) {
+        // smallest i: lowest lane, then lowest slot (i grows with the diagonal)
+        const uint64_t bal = __ballot(lm == M);
+        const int L = __builtin_ctzll(bal);
+        const int dL = g.a0 + L * K;
+        int found = C;
+#pragma unroll
+        for (int s = K - 2 + C; s >= C; s -= 2) {
+            const int v = __builtin_amdgcn_readlane(st.H[s], L);
+            if (v == M && dL + s >= vlo && dL + s <= vhi) found = s;
+        }
+        const int dm = dL + found;
+        const int mi = (r + dm) >> 1, mj = (r - dm) >> 1;
+        tr.endS = M;
+        tr.endI = mi;
+        tr.endJ = mj;
+        if (M > tr.G) {
+            tr.G = M;
+            tr.gi = mi;
+            tr.gj = mj;
+        } else if (A.Z >= 0 && mi > tr.gi && mj > tr.gj) {
+            int dd = (mi - tr.gi) - (mj - tr.gj);
+            dd = dd < 0 ? -dd : dd;
+            if (tr.G - M > A.Z + A.e2 * dd) {
+                tr.zd = 1;
+                return true;
+            }
+        }
+    }
+    return r >= g.r_last;
+}
+
+template <int K, bool MASKED>
+__device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &A, const Geo &g,
+                                          Track &tr, int r0, int lane, bool wall_lane,
+                                          int wall_pos, bool has_wall) {
+#define GA_STEP(T)                                                                   \
+    {                                                                                \
+        constexpr int C = (T) & 1;                                                   \
+        constexpr int KC = (T) >> 1;                                                 \
+        const int r = r0 + (T);                                                      \
+        if (r >= 0) {                                                                \
+            dp_step<K, C, KC>(st, A);                                                \
+            if (has_wall && (wall_pos & 1) == C) clamp_wall<K, C>(st, wall_lane, wall_pos); \
+            if (post_step<K, C, MASKED>(st, A, g, tr, r, lane)) return true;         \
+        }                                                                            \
+    }
+    GA_STEP(0)
+    GA_STEP(1)
+    GA_STEP(2)
+    GA_STEP(3)
+    GA_STEP(4)
+    GA_STEP(5)
+    GA_STEP(6)
+    GA_STEP(7)
+#undef GA_STEP
+    return false;
+}
+
+template <int K>
+__device__ void align_pair(const DpArgs &A, int p, int lane) {
+    constexpr int KH = K / 2;
+    constexpr int NW = K / 8 + 3;  // raw window words
+    Geo g;
+    g.n = A.t_len[p];
+    g.m = A.q_len[p];
+    const int n = g.n, m = g.m, w = A.w;
+    int a1;
+    if (w >= 0) {
+        g.a0 = max(-w, -m);
+        a1 = min(w, n);
+    } else {
+        g.a0 = -m;
+        a1 = n;
+    }
+    g.dlo = max(g.a0, 1 - m);
+    g.dhi = min(a1, n - 1);
+    g.D = a1 - g.a0 + 1;
+    {
+        const int dc = min(max(n - m, g.dlo), g.dhi);
+        g.r_last = min(2 * n - 2 - dc, 2 * m - 2 + dc);
+    }
+    g.fast_ok = (g.a0 == g.dlo) && (a1 == g.dhi);
+    g.fast_lo = max(-g.dlo, g.dhi);
+    g.fast_hi = min(2 * m - 2 + g.dlo, 2 * n - 2 - g.dhi);
+    const bool has_wall = g.D < WAVE * K;
+    const int wall_pos = g.D % K;
+    const bool wall_lane = has_wall && (lane == g.D / K);
+
+    const int d0 = g.a0 + lane * K;
+    PairState<K> st;
+    const int gap1 = min(A.oe1, A.oe2);
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int d = d0 + s;
+        st.H[s] = NEG;
+        st.E1[s] = NEG;
+        st.E2[s] = NEG;
+        st.F1[s] = NEG;
+        st.F2[s] = NEG;
+        if (d < g.a0 || d > a1) continue;  // outside the band: stays -inf
+        if (d == 0) st.H[s] = 0;            // origin (-1,-1), anti-diagonal -2
+        if (d == -1) {                      // boundary (-1,0), anti-diagonal -1
+            st.H[s] = -gap1;
+            st.F1[s] = -A.oe1;
+            st.F2[s] = -A.oe2;
+        }
+        if (d == 1) {  // boundary (0,-1), anti-diagonal -1
+            st.H[s] = -gap1;
+            st.E1[s] = -A.oe1;
+            st.E2[s] = -A.oe2;
+        }
+    }
+    Track tr{0, -1, -1, 0, -1, -1, 0};
+
+    const uint8_t *tbase = A.tb + 16 * A.t_off[p];
+    const uint8_t *qbase = A.qb + 16 * A.q_off[p];
+    // blocks of 8 anti-diagonals, each starting on the class of slot 0
+    int r0 = (g.a0 & 1) ? -1 : -2;
+    for (;;) {
+        // base windows of this block: T[I0 .. I0+KH+4), Q[J0-KH+1 .. J0+4)
+        const int I0 = (r0 + d0) >> 1;
+        const int J0 = (r0 - d0) >> 1;
+        const int ts = min(max(I0, -(KH + 4)), n - 1);
+        const int qs = min(max(J0 - KH + 1, -(KH + 3)), m - 1);
+        const uint32_t *tw = reinterpret_cast<const uint32_t *>(tbase + (ts - (ts & 3)));
+        const uint32_t *qw = reinterpret_cast<const uint32_t *>(qbase + (qs - (qs & 3)));
+        uint32_t RT[NW], RQ[NW], TW[NW - 1], QW[NW - 1];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            RT[k] = tw[k];
+            RQ[k] = qw[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NW - 1; ++k) {
+            TW[k] = __builtin_amdgcn_alignbyte(RT[k + 1], RT[k], (uint32_t)(ts & 3));
+            QW[k] = __builtin_amdgcn_alignbyte(RQ[k + 1], RQ[k], (uint32_t)(qs & 3));
+        }
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int c = s & 1, sp = s >> 1;
+            const uint32_t t4 = window4(TW, c + sp);
+            const uint32_t q4 = window4(QW, KH - 1 - sp);
+            const uint32_t cls = (t4 ^ q4) | ((t4 | q4) & 0x04040404u);
+            st.S4[s] = __builtin_amdgcn_perm(A.lut_hi, A.lut_lo, cls);
+        }
+        const bool fast = g.fast_ok && r0 >= g.fast_lo && r0 + 7 <= g.fast_hi;
+        const bool done = fast ? run_block<K, false>(st, A, g, tr, r0, lane, wall_lane, wall_pos, has_wall)
+                               : run_block<K, true>(st, A, g, tr, r0, lane, wall_lane, wall_pos, has_wall);
+        if (done) break;
+        r0 += 8;
+    }
+    if (lane < 7) {
+        const int v[7] = {tr.G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
+        int val = v[0];
+#pragma unroll
+        for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
+        reinterpret_cast<int32_t *>(A.out + p)[lane] = val;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void ga_dp_kernel(DpArgs A) {
+    const int lane = threadIdx.x;
+    const int count = A.counters[CNT_COUNT + A.cls];
+    for (;;) {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(&A.counters[CNT_HEAD + A.cls], 1);
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        if (idx >= count) break;
+        const int p = A.list[idx];
+        align_pair<K>(A, p, lane);
+    }
+}
+
+__global__ void ga_zero_i32(int32_t *x, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0;
+}
+
+// 2-bit words (+ N bitmap) -> one byte per base (0..3, N = 4). Thread per
+// word; the PADB guard bytes on both sides are filled with N.
+__global__ void ga_unpack(const uint32_t *words, const uint32_t *nmask, int64_t nwords,
+                          uint8_t *bytes /* points at the leading guard */) {
+    const int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (wi < nwords) {
+        const uint32_t wd = words[wi];
+        uint32_t nb = 0;
+        if (nmask) nb = (nmask[wi >> 1] >> (16 * (wi & 1))) & 0xffffu;
+        uint32_t o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int k = 4 * q + b;
+                const uint32_t c = ((nb >> k) & 1u) ? 4u : ((wd >> (2 * k)) & 3u);
+                v |= c << (8 * b);
+            }
+            o[q] = v;
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(bytes + PADB + 16 * wi);
+        *dst = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+    if (wi < 2 * PADB / 4) {  // guard words
+        uint32_t *g = reinterpret_cast<uint32_t *>(bytes);
+        const int64_t gw = wi < PADB / 4 ? wi : (PADB + 16 * nwords) / 4 + (wi - PADB / 4);
+        g[gw] = 0x04040404u;
+    }
+}
+
+struct PlanArgs {
+    int64_t n_pairs;
+    const int64_t *t_off, *q_off;
+    const int32_t *t_len, *q_len;
+    int64_t t_nwords, q_nwords;
+    int32_t max_len;
+    int32_t w;
+    int32_t *counters;
+    int32_t *lists;  // NCLASS lists of n_pairs entries
+    int32_t *err;
+    ga_result_t *out;
+};
+
+// Validate each pair, finish empty pairs, and append the rest to the work
+// list of the smallest slot count that holds the pair's diagonals.
+__global__ void ga_plan(PlanArgs A) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= A.n_pairs) return;
+    const int32_t n = A.t_len[p], m = A.q_len[p];
+    const int64_t to = A.t_off[p], qo = A.q_off[p];
+    const bool bad = n < 0 || m < 0 || n > A.max_len || m > A.max_len || to < 0 || qo < 0 ||
+                     to + (n + 15) / 16 > A.t_nwords || qo + (m + 15) / 16 > A.q_nwords;
+    if (bad) {
+        atomicOr(A.err, 1);
+        A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
+        return;
+    }
+    if (n == 0 || m == 0) {
+        A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, 0};
+        return;
+    }
+    int a0, a1;
+    if (A.w >= 0) {
+        a0 = max(-A.w, -m);
+        a1 = min(A.w, n);
+    } else {
+        a0 = -m;
+        a1 = n;
+    }
+    const int D = a1 - a0 + 1;
+    const int cls = (D + 511) / 512 - 1;
+    if (cls >= NCLASS) {
+        atomicOr(A.err, 2);
+        A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
+        return;
+    }
+    const int idx = atomicAdd(&A.counters[CNT_COUNT + cls], 1);
+    A.lists[cls * A.n_pairs + idx] = (int32_t)p;
+}
+
+// ---- packing: ASCII -> 2-bit stream + N bitmap (input packing, Section 2.2)
+
+__global__ void ga_word_counts(const int32_t *len, int64_t n, int64_t *cnt) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < n) cnt[p] = (len[p] > 0 ? (int64_t)len[p] + 15 : 0) / 16;
+}
+
+// In-place exclusive prefix sum of x[0..n) by one workgroup of 1024 threads;
+// total[0] receives the sum.
+__global__ __launch_bounds__(1024) void ga_exclusive_scan(int64_t *x, int64_t n, int64_t *total) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t lo = t * chunk, hi = min(n, lo + chunk);
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += x[i];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;  // exclusive prefix of this chunk
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t v = x[i];
+        x[i] = run;
+        run += v;
+    }
+    if (t == 1023) total[0] = part[1023];
+}
+
+__device__ __forceinline__ uint32_t base2bit(uint8_t c, bool &is_n) {
+    switch (c) {
+    case 'A': case 'a': is_n = false; return 0;
+    case 'C': case 'c': is_n = false; return 1;
+    case 'G': case 'g': is_n = false; return 2;
+    case 'T': case 't': is_n = false; return 3;
+    default: is_n = true; return 0;
+    }
+}
+
+// One workgroup per sequence; thread per output word.
+__global__ void ga_pack_kernel(const uint8_t *ascii, const int64_t *off, const int32_t *len,
+                               const int64_t *word_off, int64_t nwords, uint32_t *words,
+                               uint32_t *nmask, int32_t *err) {
+    const int64_t p = blockIdx.x;
+    const int32_t L = len[p];
+    const int64_t wo = word_off[p];
+    const int64_t nw = L > 0 ? ((int64_t)L + 15) / 16 : 0;
+    for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) {
+        const int64_t gw = wo + k;
+        if (gw < 0 || gw >= nwords) {
+            atomicOr(err, 4);
+            continue;
+        }
+        uint32_t v = 0, nb = 0;
+        for (int b = 0; b < 16; ++b) {
+            const int64_t pos = 16 * k + b;
+            if (pos >= L) break;
+            bool is_n;
+            v |= base2bit(ascii[off[p] + pos], is_n) << (2 * b);
+            nb |= (is_n ? 1u : 0u) << b;
+        }
+        words[gw] = v;
+        if (nb) atomicOr(&nmask[gw >> 1], nb << (16 * (gw & 1)));
+    }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- host side
+
+constexpr int NEVENTS = 2 + NCLASS;
+
+struct ga_context {
+    int device;
+    int num_cu;
+    void *ws;          // workspace
+    size_t ws_size;
+    int32_t *d_err;    // device error latch
+    int timing;        // record stage events in ga_align_batch
+    int timed_last;    // the last ga_align_batch recorded them
+    hipEvent_t ev[NEVENTS];
+};
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int ensure_ws(ga_context *ctx, size_t need) {
+    if (ctx->ws_size >= need) return GA_OK;
+    if (ctx->ws) {
+        hipDeviceSynchronize();
+        hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_size = 0;
+    }
+    size_t sz = align_up(need + need / 4, 1 << 20);
+    if (hipMalloc(&ctx->ws, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return GA_ENOMEM;
+    }
+    ctx->ws_size = sz;
+    return GA_OK;
+}
+
+struct SetDevice {
+    int prev = -1;
+    explicit SetDevice(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) hipSetDevice(dev);
+    }
+    ~SetDevice() {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+template <int K>
+void launch_dp(const DpArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(ga_dp_kernel<K>, dim3(grid), dim3(WAVE), 0, s, a);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ga_strerror(int code) {
+    switch (code) {
+    case GA_OK: return "ok";
+    case GA_EINVAL: return "invalid argument (null pointer, negative size or parameter, or range guard)";
+    case GA_ENOMEM: return "device workspace allocation failed";
+    case GA_EHIP: return "HIP launch or runtime error";
+    case GA_EUNSUPPORTED: return "parameters outside what the kernels implement";
+    case GA_EDEVICE: return "a device-side check failed (pair outside the declared bounds)";
+    default: return "unknown error";
+    }
+}
+
+int ga_context_create(ga_context_t **out, int device) {
+    if (!out) return GA_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return GA_EINVAL;
+    }
+    SetDevice sd(device);
+    ga_context *ctx = (ga_context *)calloc(1, sizeof(ga_context));
+    if (!ctx) return GA_ENOMEM;
+    ctx->device = device;
+    if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        ctx->num_cu = 256;
+    if (hipMalloc(&ctx->d_err, sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        free(ctx);
+        return GA_ENOMEM;
+    }
+    if (hipMemset(ctx->d_err, 0, sizeof(int32_t)) != hipSuccess) {
+        hipFree(ctx->d_err);
+        free(ctx);
+        return GA_EHIP;
+    }
+    *out = ctx;
+    return GA_OK;
+}
+
+int ga_context_destroy(ga_context_t *ctx) {
+    if (!ctx) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    hipDeviceSynchronize();
+    if (ctx->ev[0])
+        for (int k = 0; k < NEVENTS; ++k) hipEventDestroy(ctx->ev[k]);
+    if (ctx->ws) hipFree(ctx->ws);
+    if (ctx->d_err) hipFree(ctx->d_err);
+    free(ctx);
+    return GA_OK;
+}
+
+int ga_context_check(ga_context_t *ctx, void *stream) {
+    if (!ctx) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamSynchronize(s) != hipSuccess) return GA_EHIP;
+    int32_t flag = 0;
+    if (hipMemcpy(&flag, ctx->d_err, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) return GA_EHIP;
+    if (flag) {
+        if (hipMemset(ctx->d_err, 0, sizeof(int32_t)) != hipSuccess) return GA_EHIP;
+        return GA_EDEVICE;
+    }
+    return GA_OK;
+}
+
+int ga_context_set_timing(ga_context_t *ctx, int enable) {
+    if (!ctx) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    if (enable && !ctx->ev[0]) {
+        for (int k = 0; k < NEVENTS; ++k)
+            if (hipEventCreate(&ctx->ev[k]) != hipSuccess) return GA_EHIP;
+    }
+    ctx->timing = enable ? 1 : 0;
+    return GA_OK;
+}
+
+int ga_context_timing(ga_context_t *ctx, float *ms, int n) {
+    if (!ctx || !ms || n < 1) return GA_EINVAL;
+    if (!ctx->timed_last) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    if (hipEventSynchronize(ctx->ev[NEVENTS - 1]) != hipSuccess) return GA_EHIP;
+    for (int k = 0; k < n && k < NEVENTS - 1; ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ctx->ev[k], ctx->ev[k + 1]) != hipSuccess) return GA_EHIP;
+        ms[k] = t;
+    }
+    return GA_OK;
+}
+
+int ga_pair_class(int32_t n, int32_t m, int32_t w) {
+    if (n <= 0 || m <= 0) return -1;
+    int64_t a0, a1;
+    if (w >= 0) {
+        a0 = -w > -m ? -w : -m;
+        a1 = w < n ? w : n;
+    } else {
+        a0 = -m;
+        a1 = n;
+    }
+    const int64_t D = a1 - a0 + 1;
+    const int64_t cls = (D + 511) / 512 - 1;
+    return cls < NCLASS ? (int)cls : -1;
+}
+
+int64_t ga_pack_words(const int32_t *len_host, int64_t n) {
+    if (!len_host || n < 0) return -1;
+    int64_t total = 0;
+    for (int64_t p = 0; p < n; ++p) total += len_host[p] > 0 ? ((int64_t)len_host[p] + 15) / 16 : 0;
+    return total;
+}
+
+int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev, const int32_t *len_dev,
+            int64_t n, int64_t nwords, uint32_t *words_dev, int64_t *word_off_dev, uint32_t *nmask_dev,
+            void *stream) {
+    if (!ctx || n < 0 || nwords < 0) return GA_EINVAL;
+    if (n == 0) return GA_OK;
+    if (!ascii_dev || !off_dev || !len_dev || !word_off_dev) return GA_EINVAL;
+    if (nwords > 0 && (!words_dev || !nmask_dev)) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_ws(ctx, 64);
+    if (rc != GA_OK) return rc;
+    int64_t *total = (int64_t *)ctx->ws;
+    const int TB = 256;
+    hipLaunchKernelGGL(ga_word_counts, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, s, len_dev, n,
+                       word_off_dev);
+    hipLaunchKernelGGL(ga_exclusive_scan, dim3(1), dim3(1024), 0, s, word_off_dev, n, total);
+    const int64_t nmw = (nwords + 1) / 2;
+    if (nmw > 0)
+        hipLaunchKernelGGL(ga_zero_i32, dim3((unsigned)((nmw + TB - 1) / TB)), dim3(TB), 0, s,
+                           (int32_t *)nmask_dev, nmw);
+    hipLaunchKernelGGL(ga_pack_kernel, dim3((unsigned)n), dim3(64), 0, s, ascii_dev, off_dev, len_dev,
+                       word_off_dev, nwords, words_dev, nmask_dev, ctx->d_err);
+    return hipGetLastError() == hipSuccess ? GA_OK : GA_EHIP;
+}
+
+int64_t ga_count_cells(int32_t n, int32_t m, int32_t w, int32_t r_end) {
+    if (n <= 0 || m <= 0 || r_end < 0) return 0;
+    int64_t total = 0;
+    for (int64_t r = 0; r <= r_end && r <= (int64_t)n + m - 2; ++r) {
+        int64_t lo = r - (m - 1) > 0 ? r - (m - 1) : 0;
+        int64_t hi = r < n - 1 ? r : n - 1;
+        if (w >= 0) {
+            const int64_t t = r - w, u = r + w;
+            const int64_t lb = t >= 0 ? (t + 1) / 2 : -((-t) / 2);
+            const int64_t ub = u / 2;
+            if (lb > lo) lo = lb;
+            if (ub < hi) hi = ub;
+        }
+        if (hi >= lo) total += hi - lo + 1;
+    }
+    return total;
+}
+
+int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w, int32_t Z,
+                   ga_result_t *out_dev, void *stream) {
+    if (!ctx || !bt || !sc || bt->n_pairs < 0) return GA_EINVAL;
+    if (bt->n_pairs == 0) return GA_OK;
+    if (!out_dev || !bt->t_off_dev || !bt->q_off_dev || !bt->t_len_dev || !bt->q_len_dev) return GA_EINVAL;
+    if (bt->t_nwords < 0 || bt->q_nwords < 0 || bt->max_len < 0) return GA_EINVAL;
+    if ((bt->t_nwords > 0 && !bt->t_words_dev) || (bt->q_nwords > 0 && !bt->q_words_dev)) return GA_EINVAL;
+    if (sc->a < 0 || sc->b < 0 || sc->q < 0 || sc->e < 0 || sc->q2 < 0 || sc->e2 < 0 || sc->ambig < 0)
+        return GA_EINVAL;
+    if (sc->a > 127 || sc->b > 128 || sc->ambig > 128) return GA_EUNSUPPORTED;
+    {
+        const int64_t oe1 = (int64_t)sc->q + sc->e, oe2 = (int64_t)sc->q2 + sc->e2;
+        int64_t P = sc->a;
+        if (sc->b > P) P = sc->b;
+        if (sc->ambig > P) P = sc->ambig;
+        if (oe1 > P) P = oe1;
+        if (oe2 > P) P = oe2;
+        const int64_t L = 2 * (int64_t)bt->max_len + 2;
+        const int64_t guard = L * (P + sc->a + sc->e2) + (Z > 0 ? Z : 0);
+        if (guard >= (int64_t)1 << 29) return GA_EINVAL;
+    }
+    {
+        const int64_t wl = w < 0 ? bt->max_len : (w < bt->max_len ? w : bt->max_len);
+        if (2 * wl + 1 > 64 * 32) return GA_EUNSUPPORTED;
+    }
+    SetDevice sd(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t np = bt->n_pairs;
+    const size_t off_cnt = 0;
+    const size_t off_lists = 256;
+    const size_t off_tb = align_up(off_lists + sizeof(int32_t) * NCLASS * (size_t)np, 256);
+    const size_t tb_size = align_up(16 * (size_t)bt->t_nwords + 2 * PADB, 256);
+    const size_t off_qb = off_tb + tb_size;
+    const size_t qb_size = align_up(16 * (size_t)bt->q_nwords + 2 * PADB, 256);
+    const int rc = ensure_ws(ctx, off_qb + qb_size);
+    if (rc != GA_OK) return rc;
+    char *ws = (char *)ctx->ws;
+    int32_t *counters = (int32_t *)(ws + off_cnt);
+    int32_t *lists = (int32_t *)(ws + off_lists);
+    uint8_t *tb = (uint8_t *)(ws + off_tb);
+    uint8_t *qb = (uint8_t *)(ws + off_qb);
+    const int TB = 256;
+    const bool timed = ctx->timing != 0;
+    ctx->timed_last = timed ? 1 : 0;
+    if (timed) hipEventRecord(ctx->ev[0], s);
+    hipLaunchKernelGGL(ga_zero_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)CNT_WORDS);
+    {
+        const int64_t nthr = bt->t_nwords > 2 * PADB / 4 ? bt->t_nwords : 2 * PADB / 4;
+        hipLaunchKernelGGL(ga_unpack, dim3((unsigned)((nthr + TB - 1) / TB)), dim3(TB), 0, s, bt->t_words_dev,
+                           bt->t_nmask_dev, bt->t_nwords, tb);
+    }
+    {
+        const int64_t nthr = bt->q_nwords > 2 * PADB / 4 ? bt->q_nwords : 2 * PADB / 4;
+        hipLaunchKernelGGL(ga_unpack, dim3((unsigned)((nthr + TB - 1) / TB)), dim3(TB), 0, s, bt->q_words_dev,
+                           bt->q_nmask_dev, bt->q_nwords, qb);
+    }
+    PlanArgs pa;
+    pa.n_pairs = np;
+    pa.t_off = bt->t_off_dev;
+    pa.q_off = bt->q_off_dev;
+    pa.t_len = bt->t_len_dev;
+    pa.q_len = bt->q_len_dev;
+    pa.t_nwords = bt->t_nwords;
+    pa.q_nwords = bt->q_nwords;
+    pa.max_len = bt->max_len;
+    pa.w = w;
+    pa.counters = counters;
+    pa.lists = lists;
+    pa.err = ctx->d_err;
+    pa.out = out_dev;
+    hipLaunchKernelGGL(ga_plan, dim3((unsigned)((np + TB - 1) / TB)), dim3(TB), 0, s, pa);
+    if (timed) hipEventRecord(ctx->ev[1], s);
+
+    DpArgs da;
+    da.tb = tb + PADB;
+    da.qb = qb + PADB;
+    da.t_off = bt->t_off_dev;
+    da.q_off = bt->q_off_dev;
+    da.t_len = bt->t_len_dev;
+    da.q_len = bt->q_len_dev;
+    da.counters = counters;
+    da.out = out_dev;
+    da.w = w;
+    da.Z = Z;
+    da.oe1 = sc->q + sc->e;
+    da.oe2 = sc->q2 + sc->e2;
+    da.e1 = sc->e;
+    da.e2 = sc->e2;
+    {
+        const uint32_t A = (uint32_t)(uint8_t)(int8_t)sc->a;
+        const uint32_t B = (uint32_t)(uint8_t)(int8_t)(-sc->b);
+        const uint32_t N = (uint32_t)(uint8_t)(int8_t)(-sc->ambig);
+        da.lut_lo = A | (B << 8) | (B << 16) | (B << 24);
+        da.lut_hi = N | (N << 8) | (N << 16) | (N << 24);
+    }
+    const int64_t want = (int64_t)ctx->num_cu * 8;
+    const int grid = (int)(np < want ? np : want);
+    for (int c = 0; c < NCLASS; ++c) {
+        da.cls = c;
+        da.list = lists + (size_t)c * np;
+        switch (c) {
+        case 0: launch_dp<8>(da, grid, s); break;
+        case 1: launch_dp<16>(da, grid, s); break;
+        case 2: launch_dp<24>(da, grid, s); break;
+        default: launch_dp<32>(da, grid, s); break;
+        }
+        if (timed) hipEventRecord(ctx->ev[2 + c], s);
+    }
+    return hipGetLastError() == hipSuccess ? GA_OK : GA_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/ga.h declares, and its host-only functions and argument validation
+behave as documented (no GPU compute)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+import paper_2403_06478_amd as ga
+from brute import band_cells
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ga.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ga_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = ga.load_library()
+    names = _declared_functions()
+    assert names, "no declarations found"
+    assert set(names) == set(ga.ABI_SYMBOLS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_codes():
+    for code in (ga.GA_OK, ga.GA_EINVAL, ga.GA_ENOMEM, ga.GA_EHIP, ga.GA_EUNSUPPORTED, ga.GA_EDEVICE):
+        assert ga.strerror(code) and ga.strerror(code) != "unknown error"
+    assert ga.strerror(-99) == "unknown error"
+
+
+def test_count_cells_closed_form():
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        n, m = int(rng.integers(0, 60)), int(rng.integers(0, 60))
+        w = int(rng.choice([-1, 0, 1, 2, 5, 20, 100]))
+        r_end = int(rng.integers(-1, n + m))
+        want = band_cells(n, m, w, r_end) if n and m else 0
+        assert ga.ga_count_cells(n, m, w, r_end) == want, (n, m, w, r_end)
+
+
+def test_pack_words():
+    lib = ga.load_library()
+    lens = np.array([0, 1, 15, 16, 17, 33], dtype=np.int32)
+    assert lib.ga_pack_words(lens.ctypes.data, len(lens)) == 0 + 1 + 1 + 1 + 2 + 3
+    assert lib.ga_pack_words(None, 3) == -1
+
+
+def test_host_validation_without_gpu():
+    lib = ga.load_library()
+    b = ga.Batch()
+    sc = ga.scoring_struct(dict(a=2, b=4, q=4, e=2, q2=24, e2=1, ambig=1))
+    # null context / null pointers are rejected before any device work
+    assert lib.ga_align_batch(None, ctypes.byref(b), ctypes.byref(sc), 10, 10, None, None) == ga.GA_EINVAL
+    assert lib.ga_context_create(None, 0) == ga.GA_EINVAL
+    assert lib.ga_context_destroy(None) == ga.GA_EINVAL
+    assert lib.ga_context_check(None, None) == ga.GA_EINVAL
+    assert lib.ga_pack(None, None, None, None, 1, 1, None, None, None, None) == ga.GA_EINVAL

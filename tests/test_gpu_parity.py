@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, bit-exact on all seven int32 result fields."""
+
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import seqgen
+from brute import band_cells
+from gpu_util import assert_same, gpu_align, oracle_align
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+def test_cfg1_full():
+    b = seqgen.make_config(1)
+    _say(f"cfg1 full: {b.n_pairs} pairs w={b.w} Z={b.zdrop}")
+    want, _ = oracle_align(b)
+    assert_same(gpu_align(b), want, b, "cfg1")
+
+
+def test_golden_closed_forms_on_gpu():
+    from test_oracle_pins import _golden_cases
+    for c in _golden_cases():
+        b = seqgen.from_lists([c["T"]], [c["Q"]], c["sc"], c["w"], c["Z"], name=c["name"])
+        _say(f"golden {c['name']}")
+        got = gpu_align(b)
+        assert tuple(got[0]) == c["res"], (c["name"], got[0].tolist(), c["res"])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_small_batches(seed):
+    """Random scorings, bands (including 0, 1, unbanded), thresholds
+    (including 0 and disabled), N bases, related and unrelated pairs,
+    lengths 0..400 (several tiles of every slot count, ragged tails)."""
+    rng = np.random.default_rng(100 + seed)
+    for trial in range(6):
+        q = int(rng.integers(0, 8))
+        e = int(rng.integers(1, 4))
+        sc = dict(a=int(rng.integers(1, 6)), b=int(rng.integers(1, 9)), q=q, e=e,
+                  q2=q + int(rng.integers(0, 30)), e2=int(rng.integers(0, e + 1)),
+                  ambig=int(rng.integers(0, 5)))
+        w = int(rng.choice([-1, 0, 1, 2, 5, 31, 64, 100, 255, 300]))
+        Z = int(rng.choice([-1, 0, 5, 40, 200]))
+        b = seqgen.random_pairs(rng, 120, 0, 400, err=float(rng.choice([0.02, 0.1, 0.3])),
+                                n_rate=float(rng.choice([0.0, 0.01, 0.2])),
+                                related=float(rng.choice([0.3, 0.8, 1.0])), scoring=sc, w=w, zdrop=Z)
+        _say(f"random seed={seed} trial={trial} sc={sc} w={w} Z={Z}")
+        want, _ = oracle_align(b)
+        assert_same(gpu_align(b), want, b, f"seed={seed} trial={trial}")
+
+
+def test_edge_cases():
+    sc = dict(seqgen.SCORING)
+    T, Q = [], []
+    cases = [(b"", b"ACGT"), (b"ACGT", b""), (b"", b""), (b"A", b"A"), (b"A", b"C"), (b"N", b"N"),
+             (b"ACGTACGTAC" * 30, b"ACGTACGTAC" * 30), (b"N" * 200, b"N" * 150),
+             (b"ACGT" * 100, b"ACG"), (b"A", b"ACGT" * 100), (b"ACGT" * 10, b"TGCA" * 200)]
+    for t, q in cases:
+        T.append(t)
+        Q.append(q)
+    for w in (-1, 0, 1, 2, 3, 7, 64, 500, 1023):
+        for Z in (-1, 0, 3, 400):
+            b = seqgen.from_lists(T, Q, sc, w, Z)
+            want, _ = oracle_align(b)
+            assert_same(gpu_align(b), want, b, f"edge w={w} Z={Z}")
+
+
+def test_band_wider_than_sequences_and_lopsided():
+    """|n-m| > w (band cuts the corner), n or m much shorter than w, and the
+    largest band each slot count holds (2w+1 = 512, 1024, 1536, 2047)."""
+    rng = np.random.default_rng(55)
+    for w in (4, 30, 255, 511, 767, 1023):
+        b = seqgen.random_pairs(rng, 40, 1, 1500, err=0.1, n_rate=0.005, related=0.8,
+                                w=w, zdrop=int(rng.choice([-1, 100])))
+        _say(f"lopsided w={w}")
+        want, _ = oracle_align(b)
+        assert_same(gpu_align(b), want, b, f"lopsided w={w}")
+
+
+def test_cfg2_sample():
+    b = seqgen.make_config(2, n_pairs=400)
+    _say(f"cfg2 sample: {b.n_pairs} pairs")
+    want, _ = oracle_align(b)
+    assert_same(gpu_align(b), want, b, "cfg2[400]")
+
+
+def test_cfg3_sample():
+    full = seqgen.make_config(3, n_pairs=4000)
+    # keep the oracle's work bounded: drop the rare >8 kb targets
+    idx = np.nonzero(full.t_len <= 8000)[0][:1500]
+    b = full.subset(idx)
+    _say(f"cfg3 sample: {b.n_pairs} pairs")
+    want, _ = oracle_align(b)
+    got = gpu_align(b)
+    assert_same(got, want, b, "cfg3 sample")
+    # short targets cannot fall Z = 400 below their maximum, so only the
+    # longer pairs with an inserted segment drop
+    assert got[:, 6].sum() >= 1
+
+
+def test_cfg2_full_size_sampled():
+    """The bench workload at full size (100k pairs, one launch): sampled
+    pairs against the oracle, every pair against cheap properties."""
+    b = seqgen.make_config(2)
+    _say(f"cfg2 full: {b.n_pairs} pairs")
+    got = gpu_align(b)
+    rng = np.random.default_rng(2)
+    idx = np.sort(rng.choice(b.n_pairs, size=120, replace=False))
+    sub = b.subset(idx)
+    want, _ = oracle_align(sub)
+    assert_same(got[idx], want, sub, "cfg2 full sampled")
+    # properties at every pair: G >= 0, positions inside the matrix, the end
+    # on an anti-diagonal no later than the last cell, the flag binary
+    n, m = b.t_len.astype(np.int64), b.q_len.astype(np.int64)
+    assert np.all(got[:, 0] >= 0)
+    assert np.all((got[:, 1] >= -1) & (got[:, 1] < n) & (got[:, 2] >= -1) & (got[:, 2] < m))
+    assert np.all((got[:, 4] >= 0) & (got[:, 4] < n) & (got[:, 5] >= 0) & (got[:, 5] < m))
+    assert np.all(np.abs(got[:, 4] - got[:, 5]) <= b.w)
+    assert set(np.unique(got[:, 6]).tolist()) <= {0, 1}
+    assert np.all(got[:, 3] <= got[:, 0])  # the end is never above the maximum
+
+
+def test_deterministic_and_order_independent():
+    b = seqgen.make_config(2, n_pairs=300)
+    x = gpu_align(b)
+    y = gpu_align(b)
+    assert np.array_equal(x, y)
+    perm = np.random.default_rng(9).permutation(b.n_pairs)
+    z = gpu_align(b.subset(perm))
+    assert np.array_equal(z, x[perm])
+
+
+def test_suffix_invariance_after_drop():
+    """Bases beyond the termination anti-diagonal cannot change the result
+    (no cell computed ahead of the termination test leaks into it)."""
+    rng = np.random.default_rng(77)
+    b = seqgen.random_pairs(rng, 200, 200, 900, err=0.1, related=0.3, w=200, zdrop=60)
+    got = gpu_align(b)
+    T, Q = [], []
+    for p in range(b.n_pairs):
+        t, q = bytearray(b.target(p)), bytearray(b.query(p))
+        if got[p, 6]:
+            r_end = int(got[p, 4] + got[p, 5])
+            for s in (t, q):
+                for k in range(r_end + 1, len(s)):
+                    s[k] = ord("ACGTN"[(s[k] + 3 * k) % 5])
+        T.append(bytes(t))
+        Q.append(bytes(q))
+    b2 = seqgen.from_lists(T, Q, b.scoring, b.w, b.zdrop)
+    assert np.array_equal(gpu_align(b2), got)
+    assert got[:, 6].sum() > 40
+
+
+def test_unsupported_band_raises():
+    import paper_2403_06478_amd as ga
+    b = seqgen.random_pairs(np.random.default_rng(1), 4, 3000, 3000, w=2000, zdrop=5000)
+    with pytest.raises(ga.GaError) as ei:
+        gpu_align(b)
+    assert ei.value.code == ga.GA_EUNSUPPORTED
+
+
+def test_cells_closed_form():
+    import paper_2403_06478_amd as ga
+    b = seqgen.make_config(1, n_pairs=60)
+    got = gpu_align(b)
+    _, cells = oracle_align(b)
+    lib_cells = ga.count_cells(b.t_len, b.q_len, b.w, got)
+    assert np.array_equal(lib_cells, cells)
