@@ -48,7 +48,8 @@ extern "C" {
 
 /* Scoring (Section 2.1): match +a, mismatch -b, N against anything -ambig,
  * gap run of length l costs min(q + l*e, q2 + l*e2). Every field >= 0.
- * The kernels take a <= 127, b <= 128, ambig <= 128 (8-bit score table). */
+ * The kernels hold S + q + 2e in signed bytes: they take a + q + 2e <= 127,
+ * q + 2e - b >= -128 and q + 2e - ambig >= -128 (else GA_EUNSUPPORTED). */
 typedef struct {
     int32_t a, b, q, e, q2, e2, ambig;
 } ga_scoring_t;
@@ -114,7 +115,7 @@ int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
 /* Align every pair of `batch` (Section 2.1, Eq. 1-7) with band half-width w
  * (w < 0: no band) and z-drop threshold Z (Z < 0: never drop), writing
  * out_dev[p] for each pair. Range guard (GA_EINVAL otherwise):
- * (2*max_len + 2) * (max(a, b, ambig, q+e, q2+e2) + a + e2) + max(Z,0) < 2^29.
+ * (2*max_len + 2) * (max(a, b, ambig, q+e, q2+e2) + a + e + e2) + max(Z,0) < 2^29.
  * Band widths with 2*min(w, max_len) + 1 > 2048 return GA_EUNSUPPORTED. */
 int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
                    int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);

@@ -39,10 +39,10 @@
 
 namespace {
 
-constexpr int NEG = -(1 << 30);      // -inf sentinel; range guard keeps it apart
+constexpr int NEG = -(1 << 30);                  // -inf sentinel; range guard keeps it apart
 constexpr int NEG_MAX = -(1 << 30) - (1 << 29);  // below every reachable value
-constexpr int PADB = 64;             // guard bytes around the unpacked streams
-constexpr int NCLASS = 4;            // slot counts K = 8, 16, 24, 32 per lane
+constexpr int PADB = 64;                         // guard bytes around the unpacked streams
+constexpr int NCLASS = 4;                        // slot counts K = 8, 16, 24, 32 per lane
 constexpr int WAVE = 64;
 
 // Device counters (per call): [0..4) class list sizes, [4..8) class heads.
@@ -50,9 +50,19 @@ constexpr int CNT_COUNT = 0;
 constexpr int CNT_HEAD = 4;
 constexpr int CNT_WORDS = 16;
 
+// Scores are held in a frame that drifts by the piece-1 extension e per
+// anti-diagonal: a value V of a cell on anti-diagonal r is stored as
+// V + e*r. Then extending a piece-1 gap by one cell costs nothing, and the
+// other terms become constants:
+//   E1 = max(A_up, E_up)            F1 = max(A_left, F_left)
+//   E2 = max(A_up - c2, X_up)       F2 = max(A_left - c2, Y_left)
+//   H  = max(A_diag + s', E1, E2, F1, F2)
+// with A = H - q, X = E2 - d2, Y = F2 - d2, c2 = (q2+e2) - (q+e), d2 = e2 - e,
+// and s' = S + q + 2e (the substitution score with the frame's two-step
+// drift folded in; it is what the byte table holds).
 struct DpArgs {
-    const uint8_t *tb;   // unpacked target bytes; tb[16*off + k] is base k
-    const uint8_t *qb;   // unpacked query bytes
+    const uint8_t *tb;  // unpacked target bytes; tb[16*off + k] is base k
+    const uint8_t *qb;  // unpacked query bytes
     const int64_t *t_off;
     const int64_t *q_off;
     const int32_t *t_len;
@@ -62,8 +72,9 @@ struct DpArgs {
     ga_result_t *out;
     int32_t cls;
     int32_t w, Z;
-    int32_t oe1, oe2, e1, e2;
-    uint32_t lut_lo, lut_hi;  // substitution score per class byte (signed bytes)
+    int32_t q1, c2, d2, e1, e2;
+    int32_t oe1, oe2;
+    uint32_t lut_lo, lut_hi;  // s' per class byte (signed bytes)
 };
 
 __device__ __forceinline__ int dpp_from_lower_lane(int fill, int v) {
@@ -87,6 +98,21 @@ __device__ __forceinline__ int wave_max(int v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// (bit `lane` of the wave-uniform mask) ? if1 : if0, one VALU instruction.
+__device__ __forceinline__ int select_by_lanes(uint64_t mask, int if1, int if0) {
+    int r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if0), "v"(if1), "s"(mask));
+    return r;
+}
+
+__device__ __forceinline__ uint64_t lanes_from(int x) {  // lanes >= x
+    return x <= 0 ? ~0ull : (x >= 64 ? 0ull : (~0ull << x));
+}
+
+__device__ __forceinline__ uint64_t lanes_upto(int x) {  // lanes <= x
+    return x < 0 ? 0ull : (x >= 63 ? ~0ull : (~0ull >> (63 - x)));
+}
+
 __device__ __forceinline__ uint32_t window4(const uint32_t *W, int o) {
     // bytes o..o+3 of the little-endian byte array held in W (o compile-time)
     return (o & 3) ? __builtin_amdgcn_alignbyte(W[(o >> 2) + 1], W[o >> 2], (uint32_t)(o & 3))
@@ -95,86 +121,67 @@ __device__ __forceinline__ uint32_t window4(const uint32_t *W, int o) {
 
 template <int K>
 struct PairState {
-    int H[K], E1[K], E2[K], F1[K], F2[K];
-    uint32_t S4[K];  // packed scores of the slot's next 4 cells
+    int A[K], E[K], X[K], F[K], Y[K];
+    uint32_t S4[K];  // s' of the slot's next 4 cells, one signed byte each
 };
 
-// Update the slots of parity class C for cell index `kc` (0..3) of the block.
+// Update the slots of parity class C with cell index KC (0..3) of the block.
+// The band's right wall (the first diagonal past the band) sits at slot
+// `wall_pos` of the lane flagged `wall_lane`; that lane never updates the
+// wall or the dead slots after it, so they stay -inf and nothing leaks past
+// the band edge.
 template <int K, int C, int KC>
-__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &A) {
-    int hl_e = 0, e1_e = 0, e2_e = 0;  // left-edge inputs (class 0)
-    int hr_e = 0, f1_e = 0, f2_e = 0;  // right-edge inputs (class 1)
+__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, bool wall_lane, int wall_pos) {
+    int ae = 0, ee = 0, xe = 0;  // class 0: slot -1 = lower lane's slot K-1 (up)
+    int af = 0, ff = 0, yf = 0;  // class 1: slot K = upper lane's slot 0 (left)
     if (C == 0) {
-        hl_e = dpp_from_lower_lane(NEG, st.H[K - 1]);
-        e1_e = dpp_from_lower_lane(NEG, st.E1[K - 1]);
-        e2_e = dpp_from_lower_lane(NEG, st.E2[K - 1]);
+        ae = dpp_from_lower_lane(NEG, st.A[K - 1]);
+        ee = dpp_from_lower_lane(NEG, st.E[K - 1]);
+        xe = dpp_from_lower_lane(NEG, st.X[K - 1]);
     } else {
-        hr_e = dpp_from_upper_lane(NEG, st.H[0]);
-        f1_e = dpp_from_upper_lane(NEG, st.F1[0]);
-        f2_e = dpp_from_upper_lane(NEG, st.F2[0]);
+        af = dpp_from_upper_lane(NEG, st.A[0]);
+        ff = dpp_from_upper_lane(NEG, st.F[0]);
+        yf = dpp_from_upper_lane(NEG, st.Y[0]);
     }
+    // piece-2 openings of the other class, shared by both neighbours
+    int B[K];
+#pragma unroll
+    for (int s = 1 - C; s < K; s += 2) B[s] = st.A[s] - P.c2;
+    const int be = ae - P.c2, bf = af - P.c2;
 #pragma unroll
     for (int s = C; s < K; s += 2) {
-        const int hu = (s == 0) ? hl_e : st.H[s - 1];
-        const int e1u = (s == 0) ? e1_e : st.E1[s - 1];
-        const int e2u = (s == 0) ? e2_e : st.E2[s - 1];
-        const int hf = (s == K - 1) ? hr_e : st.H[s + 1];
-        const int f1l = (s == K - 1) ? f1_e : st.F1[s + 1];
-        const int f2l = (s == K - 1) ? f2_e : st.F2[s + 1];
-        const int ne1 = max(hu - A.oe1, e1u - A.e1);
-        const int ne2 = max(hu - A.oe2, e2u - A.e2);
-        const int nf1 = max(hf - A.oe1, f1l - A.e1);
-        const int nf2 = max(hf - A.oe2, f2l - A.e2);
-        const int sc = __builtin_amdgcn_sbfe((int)st.S4[s], 8 * KC, 8);
-        const int h = max(max(st.H[s] + sc, max(ne1, ne2)), max(nf1, nf2));
-        st.H[s] = h;
-        st.E1[s] = ne1;
-        st.E2[s] = ne2;
-        st.F1[s] = nf1;
-        st.F2[s] = nf2;
-    }
-}
-
-template <int K, int C>
-__device__ __forceinline__ void clamp_wall(PairState<K> &st, bool wall_lane, int wall_pos) {
-#pragma unroll
-    for (int s = C; s < K; s += 2) {
-        if (s == wall_pos) {
-            if (wall_lane) {
-                st.H[s] = NEG;
-                st.E1[s] = NEG;
-                st.E2[s] = NEG;
-                st.F1[s] = NEG;
-                st.F2[s] = NEG;
-            }
-        }
+        if (wall_lane && s >= wall_pos) continue;
+        const int au = (s == 0) ? ae : st.A[s - 1];
+        const int bu = (s == 0) ? be : B[s - 1];
+        const int eu = (s == 0) ? ee : st.E[s - 1];
+        const int xu = (s == 0) ? xe : st.X[s - 1];
+        const int al = (s == K - 1) ? af : st.A[s + 1];
+        const int bl = (s == K - 1) ? bf : B[s + 1];
+        const int fl = (s == K - 1) ? ff : st.F[s + 1];
+        const int yl = (s == K - 1) ? yf : st.Y[s + 1];
+        const int e1 = max(au, eu);
+        const int e2 = max(bu, xu);
+        const int f1 = max(al, fl);
+        const int f2 = max(bl, yl);
+        const int hd = st.A[s] + __builtin_amdgcn_sbfe((int)st.S4[s], 8 * KC, 8);
+        const int h = max(max(hd, max(e1, e2)), max(f1, f2));
+        st.A[s] = h - P.q1;
+        st.E[s] = e1;
+        st.X[s] = e2 - P.d2;
+        st.F[s] = f1;
+        st.Y[s] = f2 - P.d2;
     }
 }
 
 // Geometry of one pair (all wave-uniform).
 struct Geo {
     int n, m;
-    int a0;        // lowest diagonal held (band edge, or -m: boundary row)
-    int dlo, dhi;  // interior diagonals
+    int a0;        // lowest diagonal held (band edge, or -m: the boundary row)
+    int dlo, dhi;  // diagonals with interior cells
     int r_last;    // last non-empty anti-diagonal
-    int D;         // number of diagonals held
-    int fast_lo, fast_hi;  // anti-diagonals where every held slot is interior
+    int fast_lo, fast_hi;  // anti-diagonals on which every held slot is interior
     bool fast_ok;
 };
-
-template <int K, int C, bool MASKED>
-__device__ __forceinline__ int lane_max(const PairState<K> &st, int slo, int shi) {
-    int lm = NEG_MAX;
-#pragma unroll
-    for (int s = C; s < K; s += 2) {
-        if (MASKED) {
-            lm = (s >= slo && s <= shi) ? max(lm, st.H[s]) : lm;
-        } else {
-            lm = max(lm, st.H[s]);
-        }
-    }
-    return lm;
-}
 
 struct Track {
     int G, gi, gj;
@@ -182,31 +189,53 @@ struct Track {
     int zd;
 };
 
-// After the class-C update of anti-diagonal r: local maximum (Eq. 6),
-// global maximum (Eq. 7) and z-drop test (Eq. 5). Returns true when done.
-template <int K, int C, bool MASKED>
-__device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &A, const Geo &g,
-                                          Track &tr, int r, int lane) {
-    // interior diagonals of anti-diagonal r, clipped to its parity
-    int vlo = max(g.dlo, max(-r, r - 2 * g.m + 2));
-    int vhi = min(g.dhi, min(r, 2 * g.n - 2 - r));
+// Interior diagonals of anti-diagonal r, clipped to its parity.
+__device__ __forceinline__ void diag_window(const Geo &g, int r, int &vlo, int &vhi) {
+    vlo = max(g.dlo, max(-r, r - 2 * g.m + 2));
+    vhi = min(g.dhi, min(r, 2 * g.n - 2 - r));
     vlo += (vlo - r) & 1;
     vhi -= (vhi - r) & 1;
-    if (vlo > vhi) return r >= g.r_last;  // empty anti-diagonal: nothing to test
-    const int d0 = g.a0 + lane * K;
-    const int lm = lane_max<K, C, MASKED>(st, vlo - d0, vhi - d0);
-    const int M = wave_max(lm);
-    const bool need = (M > tr.G) || (A.Z >= 0 && tr.G - M > A.Z) || (r >= g.r_last);
+}
+
+// After the class-C update of anti-diagonal r: local maximum (Eq. 6), global
+// maximum (Eq. 7) and the z-drop test (Eq. 5). Returns true when done.
+template <int K, int C>
+__device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &P, const Geo &g,
+                                          Track &tr, int r, int lane, bool masked) {
+    int vlo = 0, vhi = 0;
+    int lm = NEG_MAX;
+    if (masked) {
+        diag_window(g, r, vlo, vhi);
+        if (vlo > vhi) return r >= g.r_last;  // no interior cell: nothing to test
+        // lanes holding slot s inside [vlo, vhi]: a lane range per slot
+        const int u = vlo - g.a0, v = vhi - g.a0;
+        const int qu = u / K, ru = u % K, qv = v / K, rv = v % K;
+        const uint64_t lo0 = lanes_from(qu), lo1 = lanes_from(qu + 1);
+        const uint64_t hi0 = lanes_upto(qv), hi1 = lanes_upto(qv - 1);
+        const int negmax = NEG_MAX;
+#pragma unroll
+        for (int s = C; s < K; s += 2) {
+            const uint64_t msk = (ru > s ? lo1 : lo0) & (rv >= s ? hi0 : hi1);
+            lm = max(lm, select_by_lanes(msk, st.A[s], negmax));
+        }
+    } else {
+#pragma unroll
+        for (int s = C; s < K; s += 2) lm = max(lm, st.A[s]);
+    }
+    const int MA = wave_max(lm);
+    const int M = MA + P.q1 - P.e1 * r;  // back to the true score
+    const bool need = (M > tr.G) || (P.Z >= 0 && tr.G - M > P.Z) || (r >= g.r_last);
     if (need) {
+        if (!masked) diag_window(g, r, vlo, vhi);
         // smallest i: lowest lane, then lowest slot (i grows with the diagonal)
-        const uint64_t bal = __ballot(lm == M);
+        const uint64_t bal = __ballot(lm == MA);
         const int L = __builtin_ctzll(bal);
         const int dL = g.a0 + L * K;
         int found = C;
 #pragma unroll
         for (int s = K - 2 + C; s >= C; s -= 2) {
-            const int v = __builtin_amdgcn_readlane(st.H[s], L);
-            if (v == M && dL + s >= vlo && dL + s <= vhi) found = s;
+            const int x = __builtin_amdgcn_readlane(st.A[s], L);
+            if (x == MA && dL + s >= vlo && dL + s <= vhi) found = s;
         }
         const int dm = dL + found;
         const int mi = (r + dm) >> 1, mj = (r - dm) >> 1;
@@ -217,10 +246,10 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
             tr.G = M;
             tr.gi = mi;
             tr.gj = mj;
-        } else if (A.Z >= 0 && mi > tr.gi && mj > tr.gj) {
+        } else if (P.Z >= 0 && mi > tr.gi && mj > tr.gj) {
             int dd = (mi - tr.gi) - (mj - tr.gj);
             dd = dd < 0 ? -dd : dd;
-            if (tr.G - M > A.Z + A.e2 * dd) {
+            if (tr.G - M > P.Z + P.e2 * dd) {
                 tr.zd = 1;
                 return true;
             }
@@ -229,20 +258,19 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
     return r >= g.r_last;
 }
 
-template <int K, bool MASKED>
-__device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &A, const Geo &g,
+template <int K>
+__device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
                                           Track &tr, int r0, int lane, bool wall_lane,
-                                          int wall_pos, bool has_wall) {
-#define GA_STEP(T)                                                                   \
-    {                                                                                \
-        constexpr int C = (T) & 1;                                                   \
-        constexpr int KC = (T) >> 1;                                                 \
-        const int r = r0 + (T);                                                      \
-        if (r >= 0) {                                                                \
-            dp_step<K, C, KC>(st, A);                                                \
-            if (has_wall && (wall_pos & 1) == C) clamp_wall<K, C>(st, wall_lane, wall_pos); \
-            if (post_step<K, C, MASKED>(st, A, g, tr, r, lane)) return true;         \
-        }                                                                            \
+                                          int wall_pos, bool masked) {
+#define GA_STEP(T)                                                                    \
+    {                                                                                 \
+        constexpr int C = (T) & 1;                                                    \
+        constexpr int KC = (T) >> 1;                                                  \
+        const int r = r0 + (T);                                                       \
+        if (r >= 0) {                                                                 \
+            dp_step<K, C, KC>(st, P, wall_lane, wall_pos);                            \
+            if (post_step<K, C>(st, P, g, tr, r, lane, masked)) return true;         \
+        }                                                                             \
     }
     GA_STEP(0)
     GA_STEP(1)
@@ -256,14 +284,61 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &A, con
     return false;
 }
 
+// Raw words holding the block's base windows T[I0 .. I0+K/2+4) and
+// Q[J0-K/2+1 .. J0+4) of this lane; starts are clamped so the loads stay
+// inside the guarded streams (a clamped lane has no interior cell there).
 template <int K>
-__device__ void align_pair(const DpArgs &A, int p, int lane) {
+struct Windows {
+    static constexpr int NW = K / 8 + 3;
+    uint32_t RT[NW], RQ[NW];
+    int to, qo;  // byte misalignment of the first word
+};
+
+template <int K>
+__device__ __forceinline__ void load_windows(Windows<K> &wd, const uint8_t *tbase, const uint8_t *qbase,
+                                             int n, int m, int r0, int d0) {
     constexpr int KH = K / 2;
-    constexpr int NW = K / 8 + 3;  // raw window words
+    const int I0 = (r0 + d0) >> 1;
+    const int J0 = (r0 - d0) >> 1;
+    const int ts = min(max(I0, -(KH + 4)), n - 1);
+    const int qs = min(max(J0 - KH + 1, -(KH + 3)), m - 1);
+    const uint32_t *tw = reinterpret_cast<const uint32_t *>(tbase + (ts - (ts & 3)));
+    const uint32_t *qw = reinterpret_cast<const uint32_t *>(qbase + (qs - (qs & 3)));
+#pragma unroll
+    for (int k = 0; k < Windows<K>::NW; ++k) {
+        wd.RT[k] = tw[k];
+        wd.RQ[k] = qw[k];
+    }
+    wd.to = ts & 3;
+    wd.qo = qs & 3;
+}
+
+template <int K>
+__device__ __forceinline__ void build_scores(PairState<K> &st, const Windows<K> &wd, const DpArgs &P) {
+    constexpr int KH = K / 2;
+    constexpr int NW = Windows<K>::NW;
+    uint32_t TW[NW - 1], QW[NW - 1];
+#pragma unroll
+    for (int k = 0; k < NW - 1; ++k) {
+        TW[k] = __builtin_amdgcn_alignbyte(wd.RT[k + 1], wd.RT[k], (uint32_t)wd.to);
+        QW[k] = __builtin_amdgcn_alignbyte(wd.RQ[k + 1], wd.RQ[k], (uint32_t)wd.qo);
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int c = s & 1, sp = s >> 1;
+        const uint32_t t4 = window4(TW, c + sp);       // T[I0+c+sp .. +4)
+        const uint32_t q4 = window4(QW, KH - 1 - sp);  // Q[J0-sp .. +4)
+        const uint32_t cls = (t4 ^ q4) | ((t4 | q4) & 0x04040404u);
+        st.S4[s] = __builtin_amdgcn_perm(P.lut_hi, P.lut_lo, cls);
+    }
+}
+
+template <int K>
+__device__ void align_pair(const DpArgs &P, int p, int lane) {
     Geo g;
-    g.n = A.t_len[p];
-    g.m = A.q_len[p];
-    const int n = g.n, m = g.m, w = A.w;
+    g.n = P.t_len[p];
+    g.m = P.q_len[p];
+    const int n = g.n, m = g.m, w = P.w;
     int a1;
     if (w >= 0) {
         g.a0 = max(-w, -m);
@@ -274,78 +349,62 @@ __device__ void align_pair(const DpArgs &A, int p, int lane) {
     }
     g.dlo = max(g.a0, 1 - m);
     g.dhi = min(a1, n - 1);
-    g.D = a1 - g.a0 + 1;
+    const int D = a1 - g.a0 + 1;
     {
         const int dc = min(max(n - m, g.dlo), g.dhi);
         g.r_last = min(2 * n - 2 - dc, 2 * m - 2 + dc);
     }
-    g.fast_ok = (g.a0 == g.dlo) && (a1 == g.dhi);
+    // fast blocks: both band edges are walls and both parities have cells
+    g.fast_ok = (g.a0 == g.dlo) && (a1 == g.dhi) && (g.dhi > g.dlo);
     g.fast_lo = max(-g.dlo, g.dhi);
     g.fast_hi = min(2 * m - 2 + g.dlo, 2 * n - 2 - g.dhi);
-    const bool has_wall = g.D < WAVE * K;
-    const int wall_pos = g.D % K;
-    const bool wall_lane = has_wall && (lane == g.D / K);
+    const bool has_wall = D < WAVE * K;
+    const int wall_pos = D % K;
+    const bool wall_lane = has_wall && (lane == D / K);
 
     const int d0 = g.a0 + lane * K;
     PairState<K> st;
-    const int gap1 = min(A.oe1, A.oe2);
+    {
+        // boundary values in the frame: origin (-1,-1) on anti-diagonal -2,
+        // (-1,0) and (0,-1) on anti-diagonal -1; everything else -inf
+        const int gap1 = min(P.oe1, P.oe2);
+        const int a_origin = -2 * P.e1 - P.q1;
+        const int a_ring = -gap1 - P.e1 - P.q1;
 #pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const int d = d0 + s;
-        st.H[s] = NEG;
-        st.E1[s] = NEG;
-        st.E2[s] = NEG;
-        st.F1[s] = NEG;
-        st.F2[s] = NEG;
-        if (d < g.a0 || d > a1) continue;  // outside the band: stays -inf
-        if (d == 0) st.H[s] = 0;            // origin (-1,-1), anti-diagonal -2
-        if (d == -1) {                      // boundary (-1,0), anti-diagonal -1
-            st.H[s] = -gap1;
-            st.F1[s] = -A.oe1;
-            st.F2[s] = -A.oe2;
-        }
-        if (d == 1) {  // boundary (0,-1), anti-diagonal -1
-            st.H[s] = -gap1;
-            st.E1[s] = -A.oe1;
-            st.E2[s] = -A.oe2;
+        for (int s = 0; s < K; ++s) {
+            const int d = d0 + s;
+            const bool held = d >= g.a0 && d <= a1;
+            st.A[s] = NEG;
+            st.E[s] = NEG;
+            st.X[s] = NEG;
+            st.F[s] = NEG;
+            st.Y[s] = NEG;
+            if (held && d == 0) st.A[s] = a_origin;
+            if (held && d == -1) {  // (-1,0): horizontal run of length 1
+                st.A[s] = a_ring;
+                st.F[s] = -P.oe1 - P.e1;
+                st.Y[s] = -P.oe2 - P.e2;
+            }
+            if (held && d == 1) {  // (0,-1): vertical run of length 1
+                st.A[s] = a_ring;
+                st.E[s] = -P.oe1 - P.e1;
+                st.X[s] = -P.oe2 - P.e2;
+            }
         }
     }
     Track tr{0, -1, -1, 0, -1, -1, 0};
 
-    const uint8_t *tbase = A.tb + 16 * A.t_off[p];
-    const uint8_t *qbase = A.qb + 16 * A.q_off[p];
+    const uint8_t *tbase = P.tb + 16 * P.t_off[p];
+    const uint8_t *qbase = P.qb + 16 * P.q_off[p];
     // blocks of 8 anti-diagonals, each starting on the class of slot 0
     int r0 = (g.a0 & 1) ? -1 : -2;
+    Windows<K> wd;
+    load_windows<K>(wd, tbase, qbase, n, m, r0, d0);
     for (;;) {
-        // base windows of this block: T[I0 .. I0+KH+4), Q[J0-KH+1 .. J0+4)
-        const int I0 = (r0 + d0) >> 1;
-        const int J0 = (r0 - d0) >> 1;
-        const int ts = min(max(I0, -(KH + 4)), n - 1);
-        const int qs = min(max(J0 - KH + 1, -(KH + 3)), m - 1);
-        const uint32_t *tw = reinterpret_cast<const uint32_t *>(tbase + (ts - (ts & 3)));
-        const uint32_t *qw = reinterpret_cast<const uint32_t *>(qbase + (qs - (qs & 3)));
-        uint32_t RT[NW], RQ[NW], TW[NW - 1], QW[NW - 1];
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            RT[k] = tw[k];
-            RQ[k] = qw[k];
-        }
-#pragma unroll
-        for (int k = 0; k < NW - 1; ++k) {
-            TW[k] = __builtin_amdgcn_alignbyte(RT[k + 1], RT[k], (uint32_t)(ts & 3));
-            QW[k] = __builtin_amdgcn_alignbyte(RQ[k + 1], RQ[k], (uint32_t)(qs & 3));
-        }
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int c = s & 1, sp = s >> 1;
-            const uint32_t t4 = window4(TW, c + sp);
-            const uint32_t q4 = window4(QW, KH - 1 - sp);
-            const uint32_t cls = (t4 ^ q4) | ((t4 | q4) & 0x04040404u);
-            st.S4[s] = __builtin_amdgcn_perm(A.lut_hi, A.lut_lo, cls);
-        }
+        build_scores<K>(st, wd, P);
+        load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, d0);  // next block, in flight
         const bool fast = g.fast_ok && r0 >= g.fast_lo && r0 + 7 <= g.fast_hi;
-        const bool done = fast ? run_block<K, false>(st, A, g, tr, r0, lane, wall_lane, wall_pos, has_wall)
-                               : run_block<K, true>(st, A, g, tr, r0, lane, wall_lane, wall_pos, has_wall);
+        const bool done = run_block<K>(st, P, g, tr, r0, lane, wall_lane, wall_pos, !fast);
         if (done) break;
         r0 += 8;
     }
@@ -354,21 +413,27 @@ __device__ void align_pair(const DpArgs &A, int p, int lane) {
         int val = v[0];
 #pragma unroll
         for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
-        reinterpret_cast<int32_t *>(A.out + p)[lane] = val;
+        reinterpret_cast<int32_t *>(P.out + p)[lane] = val;
     }
 }
 
+// Waves per SIMD each slot count is compiled for (register budget).
 template <int K>
-__global__ __launch_bounds__(64) void ga_dp_kernel(DpArgs A) {
+struct Occ {
+    static constexpr int value = K <= 8 ? 4 : (K <= 16 ? 3 : 2);
+};
+
+template <int K>
+__global__ __launch_bounds__(64, Occ<K>::value) void ga_dp_kernel(DpArgs P) {
     const int lane = threadIdx.x;
-    const int count = A.counters[CNT_COUNT + A.cls];
+    const int count = P.counters[CNT_COUNT + P.cls];
     for (;;) {
         int idx = 0;
-        if (lane == 0) idx = atomicAdd(&A.counters[CNT_HEAD + A.cls], 1);
+        if (lane == 0) idx = atomicAdd(&P.counters[CNT_HEAD + P.cls], 1);
         idx = __builtin_amdgcn_readfirstlane(idx);
         if (idx >= count) break;
-        const int p = A.list[idx];
-        align_pair<K>(A, p, lane);
+        const int p = P.list[idx];
+        align_pair<K>(P, p, lane);
     }
 }
 
@@ -552,8 +617,8 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int ensure_ws(ga_context *ctx, size_t need) {
     if (ctx->ws_size >= need) return GA_OK;
     if (ctx->ws) {
-        hipDeviceSynchronize();
-        hipFree(ctx->ws);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->ws);
         ctx->ws = nullptr;
         ctx->ws_size = 0;
     }
@@ -750,7 +815,11 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     if ((bt->t_nwords > 0 && !bt->t_words_dev) || (bt->q_nwords > 0 && !bt->q_words_dev)) return GA_EINVAL;
     if (sc->a < 0 || sc->b < 0 || sc->q < 0 || sc->e < 0 || sc->q2 < 0 || sc->e2 < 0 || sc->ambig < 0)
         return GA_EINVAL;
-    if (sc->a > 127 || sc->b > 128 || sc->ambig > 128) return GA_EUNSUPPORTED;
+    {
+        // the per-cell score table holds S + q + 2e in signed bytes
+        const int64_t fold = (int64_t)sc->q + 2 * (int64_t)sc->e;
+        if (sc->a + fold > 127 || fold - sc->b < -128 || fold - sc->ambig < -128) return GA_EUNSUPPORTED;
+    }
     {
         const int64_t oe1 = (int64_t)sc->q + sc->e, oe2 = (int64_t)sc->q2 + sc->e2;
         int64_t P = sc->a;
@@ -759,7 +828,7 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         if (oe1 > P) P = oe1;
         if (oe2 > P) P = oe2;
         const int64_t L = 2 * (int64_t)bt->max_len + 2;
-        const int64_t guard = L * (P + sc->a + sc->e2) + (Z > 0 ? Z : 0);
+        const int64_t guard = L * (P + sc->a + sc->e + sc->e2) + (Z > 0 ? Z : 0);
         if (guard >= (int64_t)1 << 29) return GA_EINVAL;
     }
     {
@@ -825,14 +894,18 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     da.out = out_dev;
     da.w = w;
     da.Z = Z;
-    da.oe1 = sc->q + sc->e;
-    da.oe2 = sc->q2 + sc->e2;
+    da.q1 = sc->q;
+    da.c2 = (sc->q2 + sc->e2) - (sc->q + sc->e);
+    da.d2 = sc->e2 - sc->e;
     da.e1 = sc->e;
     da.e2 = sc->e2;
+    da.oe1 = sc->q + sc->e;
+    da.oe2 = sc->q2 + sc->e2;
     {
-        const uint32_t A = (uint32_t)(uint8_t)(int8_t)sc->a;
-        const uint32_t B = (uint32_t)(uint8_t)(int8_t)(-sc->b);
-        const uint32_t N = (uint32_t)(uint8_t)(int8_t)(-sc->ambig);
+        const int fold = sc->q + 2 * sc->e;  // frame drift over the diagonal step
+        const uint32_t A = (uint32_t)(uint8_t)(int8_t)(sc->a + fold);
+        const uint32_t B = (uint32_t)(uint8_t)(int8_t)(fold - sc->b);
+        const uint32_t N = (uint32_t)(uint8_t)(int8_t)(fold - sc->ambig);
         da.lut_lo = A | (B << 8) | (B << 16) | (B << 24);
         da.lut_hi = N | (N << 8) | (N << 16) | (N << 24);
     }
