@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs (profiling runs only)")
     ap.add_argument("--cpu-sample", type=int, default=1200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy (scales rocprofv3 byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -133,6 +135,15 @@ def main():
     elapsed = t1 - t0
     ms_per_step = elapsed / args.steps * 1e3
     log(f"{ms_per_step:.2f} ms per step")
+
+    if args.copy_calibration:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 536870912 bytes read + 536870912 bytes written")
+        del src, dst
 
     res = out.cpu().numpy()
     t_len, q_len = batch.t_len, batch.q_len

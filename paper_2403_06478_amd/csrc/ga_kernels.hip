@@ -125,13 +125,56 @@ struct PairState {
     uint32_t S4[K];  // s' of the slot's next 4 cells, one signed byte each
 };
 
+// One slot update (class C slot S, block cell KC). Inputs come from the
+// other class (anti-diagonal r-1) and the slot's own A (anti-diagonal r-2).
+template <int K, int S, int KC>
+__device__ __forceinline__ void update_slot(PairState<K> &st, const DpArgs &P, const int (&B)[K],
+                                            int ae, int be, int ee, int xe, int af, int bf, int ff,
+                                            int yf) {
+    const int au = (S == 0) ? ae : st.A[S == 0 ? 0 : S - 1];
+    const int bu = (S == 0) ? be : B[S == 0 ? 0 : S - 1];
+    const int eu = (S == 0) ? ee : st.E[S == 0 ? 0 : S - 1];
+    const int xu = (S == 0) ? xe : st.X[S == 0 ? 0 : S - 1];
+    const int al = (S == K - 1) ? af : st.A[S == K - 1 ? 0 : S + 1];
+    const int bl = (S == K - 1) ? bf : B[S == K - 1 ? 0 : S + 1];
+    const int fl = (S == K - 1) ? ff : st.F[S == K - 1 ? 0 : S + 1];
+    const int yl = (S == K - 1) ? yf : st.Y[S == K - 1 ? 0 : S + 1];
+    const int e1 = max(au, eu);
+    const int e2 = max(bu, xu);
+    const int f1 = max(al, fl);
+    const int f2 = max(bl, yl);
+    const int hd = st.A[S] + __builtin_amdgcn_sbfe((int)st.S4[S], 8 * KC, 8);
+    const int h = max(max(hd, max(e1, e2)), max(f1, f2));
+    st.A[S] = h - P.q1;
+    st.E[S] = e1;
+    st.X[S] = e2 - P.d2;
+    st.F[S] = f1;
+    st.Y[S] = f2 - P.d2;
+}
+
 // Update the slots of parity class C with cell index KC (0..3) of the block.
-// The band's right wall (the first diagonal past the band) sits at slot
-// `wall_pos` of the lane flagged `wall_lane`; that lane never updates the
-// wall or the dead slots after it, so they stay -inf and nothing leaks past
-// the band edge.
+// The band's right wall (the first diagonal past the band) is slot
+// `wall_pos` of the lanes set in `wall_lanes`; those lanes never update it,
+// so it stays -inf. Slots beyond the wall read only the wall and each other,
+// so they stay -inf too, and nothing crosses the band edge.
+template <int K, int C, int KC, int S>
+__device__ __forceinline__ void update_class(PairState<K> &st, const DpArgs &P, const int (&B)[K],
+                                             int ae, int be, int ee, int xe, int af, int bf, int ff,
+                                             int yf, uint64_t wall_lanes, int wall_pos, int lane) {
+    if constexpr (S < K) {
+        // lanes that skip this slot: the wall lane if this is the wall slot
+        const uint64_t skip = (S == wall_pos) ? wall_lanes : 0ull;
+        if (!__builtin_amdgcn_inverse_ballot_w64(skip))
+            update_slot<K, S, KC>(st, P, B, ae, be, ee, xe, af, bf, ff, yf);
+        update_class<K, C, KC, S + 2>(st, P, B, ae, be, ee, xe, af, bf, ff, yf, wall_lanes, wall_pos, lane);
+    }
+}
+
 template <int K, int C, int KC>
-__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, bool wall_lane, int wall_pos) {
+__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, uint64_t wall_lanes, int wall_pos,
+                                        int lane) {
+    // recomputed every step rather than hoisted out of the loop as 2*K SGPRs
+    asm volatile("" : "+s"(wall_lanes), "+s"(wall_pos));
     int ae = 0, ee = 0, xe = 0;  // class 0: slot -1 = lower lane's slot K-1 (up)
     int af = 0, ff = 0, yf = 0;  // class 1: slot K = upper lane's slot 0 (left)
     if (C == 0) {
@@ -146,31 +189,9 @@ __device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, bool 
     // piece-2 openings of the other class, shared by both neighbours
     int B[K];
 #pragma unroll
-    for (int s = 1 - C; s < K; s += 2) B[s] = st.A[s] - P.c2;
+    for (int s = 0; s < K; ++s) B[s] = ((s & 1) != C) ? st.A[s] - P.c2 : 0;
     const int be = ae - P.c2, bf = af - P.c2;
-#pragma unroll
-    for (int s = C; s < K; s += 2) {
-        if (wall_lane && s >= wall_pos) continue;
-        const int au = (s == 0) ? ae : st.A[s - 1];
-        const int bu = (s == 0) ? be : B[s - 1];
-        const int eu = (s == 0) ? ee : st.E[s - 1];
-        const int xu = (s == 0) ? xe : st.X[s - 1];
-        const int al = (s == K - 1) ? af : st.A[s + 1];
-        const int bl = (s == K - 1) ? bf : B[s + 1];
-        const int fl = (s == K - 1) ? ff : st.F[s + 1];
-        const int yl = (s == K - 1) ? yf : st.Y[s + 1];
-        const int e1 = max(au, eu);
-        const int e2 = max(bu, xu);
-        const int f1 = max(al, fl);
-        const int f2 = max(bl, yl);
-        const int hd = st.A[s] + __builtin_amdgcn_sbfe((int)st.S4[s], 8 * KC, 8);
-        const int h = max(max(hd, max(e1, e2)), max(f1, f2));
-        st.A[s] = h - P.q1;
-        st.E[s] = e1;
-        st.X[s] = e2 - P.d2;
-        st.F[s] = f1;
-        st.Y[s] = f2 - P.d2;
-    }
+    update_class<K, C, KC, C>(st, P, B, ae, be, ee, xe, af, bf, ff, yf, wall_lanes, wall_pos, lane);
 }
 
 // Geometry of one pair (all wave-uniform).
@@ -260,7 +281,7 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
 
 template <int K>
 __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
-                                          Track &tr, int r0, int lane, bool wall_lane,
+                                          Track &tr, int r0, int lane, uint64_t wall_lanes,
                                           int wall_pos, bool masked) {
 #define GA_STEP(T)                                                                    \
     {                                                                                 \
@@ -268,7 +289,7 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
         constexpr int KC = (T) >> 1;                                                  \
         const int r = r0 + (T);                                                       \
         if (r >= 0) {                                                                 \
-            dp_step<K, C, KC>(st, P, wall_lane, wall_pos);                            \
+            dp_step<K, C, KC>(st, P, wall_lanes, wall_pos, lane);                     \
             if (post_step<K, C>(st, P, g, tr, r, lane, masked)) return true;         \
         }                                                                             \
     }
@@ -360,7 +381,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane) {
     g.fast_hi = min(2 * m - 2 + g.dlo, 2 * n - 2 - g.dhi);
     const bool has_wall = D < WAVE * K;
     const int wall_pos = D % K;
-    const bool wall_lane = has_wall && (lane == D / K);
+    const uint64_t wall_lanes = has_wall ? (1ull << (D / K)) : 0ull;
 
     const int d0 = g.a0 + lane * K;
     PairState<K> st;
@@ -404,7 +425,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane) {
         build_scores<K>(st, wd, P);
         load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, d0);  // next block, in flight
         const bool fast = g.fast_ok && r0 >= g.fast_lo && r0 + 7 <= g.fast_hi;
-        const bool done = run_block<K>(st, P, g, tr, r0, lane, wall_lane, wall_pos, !fast);
+        const bool done = run_block<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, !fast);
         if (done) break;
         r0 += 8;
     }
