@@ -144,7 +144,7 @@ __device__ __forceinline__ void update_slot(PairState<K> &st, const DpArgs &P, c
     const int f1 = max(al, fl);
     const int f2 = max(bl, yl);
     const int hd = st.A[S] + __builtin_amdgcn_sbfe((int)st.S4[S], 8 * KC, 8);
-    const int h = max(max(hd, max(e1, e2)), max(f1, f2));
+    const int h = max(max(max(max(hd, e1), e2), f1), f2);  // two v_max3
     st.A[S] = h - P.q1;
     st.E[S] = e1;
     st.X[S] = e2 - P.d2;
@@ -205,9 +205,14 @@ struct Geo {
 };
 
 struct Track {
-    int G, gi, gj;
-    int endS, endI, endJ;
+    int G, gi, gj;        // global maximum (Eq. 7); gi/gj valid once resolved
+    int endS, endI, endJ; // local maximum where the sweep ended
     int zd;
+    // where G was taken, kept lazily: the anti-diagonal, the lane holding
+    // the cell, the slot class and the frame value; that lane's class values
+    // are parked in LDS until the cell is needed
+    int g_r, g_lane, g_cls, g_ma;
+    bool g_open;
 };
 
 // Interior diagonals of anti-diagonal r, clipped to its parity.
@@ -218,11 +223,48 @@ __device__ __forceinline__ void diag_window(const Geo &g, int r, int &vlo, int &
     vhi -= (vhi - r) & 1;
 }
 
+// Smallest-i cell attaining the frame value MA among the class-C slots of
+// anti-diagonal r whose diagonals lie in [vlo, vhi] (lowest lane first, then
+// lowest slot: i grows with the diagonal).
+template <int K, int C>
+__device__ __forceinline__ void locate(const PairState<K> &st, const Geo &g, int lm, int MA, int r,
+                                       int vlo, int vhi, int &mi, int &mj) {
+    const uint64_t bal = __ballot(lm == MA);
+    const int L = __builtin_ctzll(bal);
+    const int dL = g.a0 + L * K;
+    int found = C;
+#pragma unroll
+    for (int s = K - 2 + C; s >= C; s -= 2) {
+        const int x = __builtin_amdgcn_readlane(st.A[s], L);
+        if (x == MA && dL + s >= vlo && dL + s <= vhi) found = s;
+    }
+    const int dm = dL + found;
+    mi = (r + dm) >> 1;
+    mj = (r - dm) >> 1;
+}
+
+// The cell of the global maximum from the values parked in LDS.
+template <int K>
+__device__ __forceinline__ void resolve_g(Track &tr, const Geo &g, const int *park, int lane) {
+    if (!tr.g_open) return;
+    int vlo, vhi;
+    diag_window(g, tr.g_r, vlo, vhi);
+    const int dL = g.a0 + tr.g_lane * K + tr.g_cls;
+    const int t = lane < K / 2 ? lane : 0;
+    const int d = dL + 2 * t;
+    const bool hit = lane < K / 2 && park[t] == tr.g_ma && d >= vlo && d <= vhi;
+    const int first = __builtin_ctzll(__ballot(hit));
+    const int dm = dL + 2 * first;
+    tr.gi = (tr.g_r + dm) >> 1;
+    tr.gj = (tr.g_r - dm) >> 1;
+    tr.g_open = false;
+}
+
 // After the class-C update of anti-diagonal r: local maximum (Eq. 6), global
 // maximum (Eq. 7) and the z-drop test (Eq. 5). Returns true when done.
 template <int K, int C>
 __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &P, const Geo &g,
-                                          Track &tr, int r, int lane, bool masked) {
+                                          Track &tr, int r, int lane, bool masked, int *park) {
     int vlo = 0, vhi = 0;
     int lm = NEG_MAX;
     if (masked) {
@@ -245,44 +287,53 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
     }
     const int MA = wave_max(lm);
     const int M = MA + P.q1 - P.e1 * r;  // back to the true score
-    const bool need = (M > tr.G) || (P.Z >= 0 && tr.G - M > P.Z) || (r >= g.r_last);
-    if (need) {
-        if (!masked) diag_window(g, r, vlo, vhi);
-        // smallest i: lowest lane, then lowest slot (i grows with the diagonal)
-        const uint64_t bal = __ballot(lm == MA);
-        const int L = __builtin_ctzll(bal);
-        const int dL = g.a0 + L * K;
-        int found = C;
+    const bool last = r >= g.r_last;
+    if (M > tr.G) {
+        // new global maximum: park the holding lane's class values
+        const int L = __builtin_ctzll(__ballot(lm == MA));
+        if (lane == L) {
 #pragma unroll
-        for (int s = K - 2 + C; s >= C; s -= 2) {
-            const int x = __builtin_amdgcn_readlane(st.A[s], L);
-            if (x == MA && dL + s >= vlo && dL + s <= vhi) found = s;
+            for (int s = C; s < K; s += 2) park[s >> 1] = st.A[s];
         }
-        const int dm = dL + found;
-        const int mi = (r + dm) >> 1, mj = (r - dm) >> 1;
+        tr.G = M;
+        tr.g_r = r;
+        tr.g_lane = L;
+        tr.g_cls = C;
+        tr.g_ma = MA;
+        tr.g_open = true;
+        if (last) {
+            if (!masked) diag_window(g, r, vlo, vhi);
+            locate<K, C>(st, g, lm, MA, r, vlo, vhi, tr.endI, tr.endJ);
+            tr.endS = M;
+        }
+        return last;
+    }
+    if ((P.Z >= 0 && tr.G - M > P.Z) || last) {
+        if (!masked) diag_window(g, r, vlo, vhi);
+        int mi, mj;
+        locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
         tr.endS = M;
         tr.endI = mi;
         tr.endJ = mj;
-        if (M > tr.G) {
-            tr.G = M;
-            tr.gi = mi;
-            tr.gj = mj;
-        } else if (P.Z >= 0 && mi > tr.gi && mj > tr.gj) {
-            int dd = (mi - tr.gi) - (mj - tr.gj);
-            dd = dd < 0 ? -dd : dd;
-            if (tr.G - M > P.Z + P.e2 * dd) {
-                tr.zd = 1;
-                return true;
+        if (P.Z >= 0 && tr.G - M > P.Z) {
+            resolve_g<K>(tr, g, park, lane);
+            if (mi > tr.gi && mj > tr.gj) {
+                int dd = (mi - tr.gi) - (mj - tr.gj);
+                dd = dd < 0 ? -dd : dd;
+                if (tr.G - M > P.Z + P.e2 * dd) {
+                    tr.zd = 1;
+                    return true;
+                }
             }
         }
     }
-    return r >= g.r_last;
+    return last;
 }
 
 template <int K>
 __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
                                           Track &tr, int r0, int lane, uint64_t wall_lanes,
-                                          int wall_pos, bool masked) {
+                                          int wall_pos, bool masked, int *park) {
 #define GA_STEP(T)                                                                    \
     {                                                                                 \
         constexpr int C = (T) & 1;                                                    \
@@ -290,7 +341,7 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
         const int r = r0 + (T);                                                       \
         if (r >= 0) {                                                                 \
             dp_step<K, C, KC>(st, P, wall_lanes, wall_pos, lane);                     \
-            if (post_step<K, C>(st, P, g, tr, r, lane, masked)) return true;         \
+            if (post_step<K, C>(st, P, g, tr, r, lane, masked, park)) return true;   \
         }                                                                             \
     }
     GA_STEP(0)
@@ -355,7 +406,7 @@ __device__ __forceinline__ void build_scores(PairState<K> &st, const Windows<K> 
 }
 
 template <int K>
-__device__ void align_pair(const DpArgs &P, int p, int lane) {
+__device__ void align_pair(const DpArgs &P, int p, int lane, int *park) {
     Geo g;
     g.n = P.t_len[p];
     g.m = P.q_len[p];
@@ -413,7 +464,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane) {
             }
         }
     }
-    Track tr{0, -1, -1, 0, -1, -1, 0};
+    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false};
 
     const uint8_t *tbase = P.tb + 16 * P.t_off[p];
     const uint8_t *qbase = P.qb + 16 * P.q_off[p];
@@ -425,10 +476,11 @@ __device__ void align_pair(const DpArgs &P, int p, int lane) {
         build_scores<K>(st, wd, P);
         load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, d0);  // next block, in flight
         const bool fast = g.fast_ok && r0 >= g.fast_lo && r0 + 7 <= g.fast_hi;
-        const bool done = run_block<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, !fast);
+        const bool done = run_block<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, !fast, park);
         if (done) break;
         r0 += 8;
     }
+    resolve_g<K>(tr, g, park, lane);
     if (lane < 7) {
         const int v[7] = {tr.G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
         int val = v[0];
@@ -446,6 +498,7 @@ struct Occ {
 
 template <int K>
 __global__ __launch_bounds__(64, Occ<K>::value) void ga_dp_kernel(DpArgs P) {
+    __shared__ int park[K / 2];  // class values of the lane that holds the global maximum
     const int lane = threadIdx.x;
     const int count = P.counters[CNT_COUNT + P.cls];
     for (;;) {
@@ -454,7 +507,7 @@ __global__ __launch_bounds__(64, Occ<K>::value) void ga_dp_kernel(DpArgs P) {
         idx = __builtin_amdgcn_readfirstlane(idx);
         if (idx >= count) break;
         const int p = P.list[idx];
-        align_pair<K>(P, p, lane);
+        align_pair<K>(P, p, lane, park);
     }
 }
 
