@@ -121,7 +121,11 @@ __device__ __forceinline__ uint32_t window4(const uint32_t *W, int o) {
 
 template <int K>
 struct PairState {
-    int A[K], E[K], X[K], F[K], Y[K];
+    // A, E and X are register vectors so the wall slot can be indexed at its
+    // wave-uniform position (s_set_gpr_idx) without leaving registers.
+    typedef int VecK __attribute__((ext_vector_type(K)));
+    VecK A, E, X;
+    int F[K], Y[K];
     uint32_t S4[K];  // s' of the slot's next 4 cells, one signed byte each
 };
 
@@ -152,29 +156,20 @@ __device__ __forceinline__ void update_slot(PairState<K> &st, const DpArgs &P, c
     st.Y[S] = f2 - P.d2;
 }
 
-// Update the slots of parity class C with cell index KC (0..3) of the block.
-// The band's right wall (the first diagonal past the band) is slot
-// `wall_pos` of the lanes set in `wall_lanes`; those lanes never update it,
-// so it stays -inf. Slots beyond the wall read only the wall and each other,
-// so they stay -inf too, and nothing crosses the band edge.
-template <int K, int C, int KC, int S>
+// Slots S, S+2, ... of one parity class (static unroll).
+template <int K, int KC, int S>
 __device__ __forceinline__ void update_class(PairState<K> &st, const DpArgs &P, const int (&B)[K],
                                              int ae, int be, int ee, int xe, int af, int bf, int ff,
-                                             int yf, uint64_t wall_lanes, int wall_pos, int lane) {
+                                             int yf) {
     if constexpr (S < K) {
-        // lanes that skip this slot: the wall lane if this is the wall slot
-        const uint64_t skip = (S == wall_pos) ? wall_lanes : 0ull;
-        if (!__builtin_amdgcn_inverse_ballot_w64(skip))
-            update_slot<K, S, KC>(st, P, B, ae, be, ee, xe, af, bf, ff, yf);
-        update_class<K, C, KC, S + 2>(st, P, B, ae, be, ee, xe, af, bf, ff, yf, wall_lanes, wall_pos, lane);
+        update_slot<K, S, KC>(st, P, B, ae, be, ee, xe, af, bf, ff, yf);
+        update_class<K, KC, S + 2>(st, P, B, ae, be, ee, xe, af, bf, ff, yf);
     }
 }
 
+// Update the slots of parity class C with cell index KC (0..3) of the block.
 template <int K, int C, int KC>
-__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, uint64_t wall_lanes, int wall_pos,
-                                        int lane) {
-    // recomputed every step rather than hoisted out of the loop as 2*K SGPRs
-    asm volatile("" : "+s"(wall_lanes), "+s"(wall_pos));
+__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P) {
     int ae = 0, ee = 0, xe = 0;  // class 0: slot -1 = lower lane's slot K-1 (up)
     int af = 0, ff = 0, yf = 0;  // class 1: slot K = upper lane's slot 0 (left)
     if (C == 0) {
@@ -191,7 +186,21 @@ __device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, uint6
 #pragma unroll
     for (int s = 0; s < K; ++s) B[s] = ((s & 1) != C) ? st.A[s] - P.c2 : 0;
     const int be = ae - P.c2, bf = af - P.c2;
-    update_class<K, C, KC, C>(st, P, B, ae, be, ee, xe, af, bf, ff, yf, wall_lanes, wall_pos, lane);
+    update_class<K, KC, C>(st, P, B, ae, be, ee, xe, af, bf, ff, yf);
+}
+
+// The band's right wall is the first diagonal past the band: slot
+// `wall_pos` of the lane flagged in `wall_lanes`. After each update of its
+// class it is forced back to -inf there; its A, E and X are all it feeds
+// forward, so the dead slots beyond it never leave -inf either and nothing
+// crosses the band edge.
+template <int K>
+__device__ __forceinline__ void clamp_wall(PairState<K> &st, uint64_t wall_lanes, int wall_pos) {
+    const bool wl = __builtin_amdgcn_inverse_ballot_w64(wall_lanes);
+    const int wp = __builtin_amdgcn_readfirstlane(wall_pos);
+    st.A[wp] = wl ? NEG : st.A[wp];
+    st.E[wp] = wl ? NEG : st.E[wp];
+    st.X[wp] = wl ? NEG : st.X[wp];
 }
 
 // Geometry of one pair (all wave-uniform).
@@ -340,7 +349,8 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
         constexpr int KC = (T) >> 1;                                                  \
         const int r = r0 + (T);                                                       \
         if (r >= 0) {                                                                 \
-            dp_step<K, C, KC>(st, P, wall_lanes, wall_pos, lane);                     \
+            dp_step<K, C, KC>(st, P);                                                 \
+            if (wall_lanes != 0 && (wall_pos & 1) == C) clamp_wall<K>(st, wall_lanes, wall_pos); \
             if (post_step<K, C>(st, P, g, tr, r, lane, masked, park)) return true;   \
         }                                                                             \
     }
