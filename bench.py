@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs (profiling runs only)")
-    ap.add_argument("--cpu-sample", type=int, default=1200)
+    ap.add_argument("--cpu-sample", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (scales rocprofv3 byte counters)")
