@@ -46,12 +46,16 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(cls_name: str):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
-    if there is none or the kernel source changed since it was taken."""
+def read_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
+    summary, or None if there is none for it or the kernel source changed
+    since it was taken."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     text = open(PMC_SUMMARY).read()
+    m = re.search(r"kernel:\s*(\S+)", text)
+    if not m or m.group(1) != kernel:
+        return None
     m = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", text)
     if not m or m.group(1) != kernel_source_hash():
         return None
@@ -153,18 +157,24 @@ def main():
     gcups = total_cells / (ms_per_step / 1e3) / 1e9
     pairs_per_s = batch.n_pairs / (ms_per_step / 1e3)
 
-    stage = np.array(stage_ms)  # [steps, 5]
+    stage = np.array(stage_ms)  # [steps, 1 + classes]
     mean_ms = stage.mean(axis=0)
     dom = int(np.argmax(mean_ms[1:]))
     dom_cells = int(cells[cls == dom].sum())
     achieved = OPS_PER_CELL * dom_cells / (mean_ms[1 + dom] / 1e3) / 1e12
-    traffic = read_traffic(f"k{ga.CLASS_SLOTS[dom]}")
+    traffic = read_traffic(ga.class_name(dom))
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": f"ga_dp_kernel<{ga.CLASS_SLOTS[dom]}>",
+                "kernel": ga.class_name(dom),
                 "kernel_ms": round(float(mean_ms[1 + dom]), 3),
                 "kernel_cells": dom_cells, "ops_per_cell": OPS_PER_CELL}
-    log(f"stages ms (prep, K8, K16, K24, K32): {[round(float(x), 3) for x in mean_ms]}")
+    log(f"stages ms (prep, then {', '.join(ga.class_name(c) for c in range(len(ga.CLASSES)))}): "
+        f"{[round(float(x), 3) for x in mean_ms]}")
+
+    measured_peak = ctx.calibrate_valu(stream) / 1e12
+    roofline["peak_measured"] = round(measured_peak, 2)
+    roofline["frac_measured"] = round(achieved / measured_peak, 4)
+    log(f"measured int32 VALU peak {measured_peak:.2f} T lane-ops/s")
 
     cpu = None
     if not args.no_cpu_baseline:

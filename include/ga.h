@@ -116,7 +116,7 @@ int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
  * (w < 0: no band) and z-drop threshold Z (Z < 0: never drop), writing
  * out_dev[p] for each pair. Range guard (GA_EINVAL otherwise):
  * (2*max_len + 2) * (max(a, b, ambig, q+e, q2+e2) + a + e + e2) + max(Z,0) < 2^29.
- * Band widths with 2*min(w, max_len) + 1 > 2048 return GA_EUNSUPPORTED. */
+ * Band widths with 2*min(w, max_len) + 1 > 8192 return GA_EUNSUPPORTED. */
 int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
                    int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);
 
@@ -126,14 +126,24 @@ int ga_context_set_timing(ga_context_t *ctx, int enable);
 
 /* Milliseconds spent by the stages of the last timed ga_align_batch on this
  * context (waits for those events): ms[0] = unpack + planning kernels,
- * ms[1+c] = the alignment kernel of slot class c (K = 8, 16, 24, 32 slots
- * per lane), for c < n-1. GA_EINVAL if timing was off for that call. */
+ * ms[1+c] = the alignment kernel of class c, for c < n-1 and c < 8. Class c
+ * runs K slots per lane and W waves per pair, holding bands of up to 64*K*W
+ * diagonals: (K, W) = (8,1) (16,1) (24,1) (32,1) (24,2) (32,2) (32,3) (32,4).
+ * GA_EINVAL if timing was off for that call. */
 int ga_context_timing(ga_context_t *ctx, float *ms, int n);
 
-/* Slot class (0..3) that ga_align_batch uses for a pair of lengths n, m at
- * band w, or -1 for an empty pair or a band wider than the kernels hold.
+/* Class (0..7, see ga_context_timing) that ga_align_batch uses for a pair
+ * of lengths n, m at band w: the first whose kernel holds the band's
+ * min(w, n) + min(w, m) + 1 diagonals (all n + m + 1 when w < 0); -1 for an
+ * empty pair or a band wider than the kernels hold.
  * Host function, for attributing work to the per-class kernels. */
 int ga_pair_class(int32_t n, int32_t m, int32_t w);
+
+/* Measured integer VALU peak of the context's device, for rooflines: a
+ * probe kernel of independent v_max3_i32 / v_add_u32 chains (8 waves per
+ * SIMD on every CU) is timed with HIP events on `stream`; *lane_ops_per_s
+ * receives int32 lane-operations per second. Synchronises `stream`. */
+int ga_calibrate_valu(ga_context_t *ctx, double *lane_ops_per_s, void *stream);
 
 /* Algorithmic work of one pair: the number of in-band cells (i,j),
  * 0 <= i < n, 0 <= j < m, on anti-diagonals 0..r_end (r_end = end_i+end_j);

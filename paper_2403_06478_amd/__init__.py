@@ -30,10 +30,19 @@ RESULT_FIELDS = ("max_score", "max_i", "max_j", "end_score", "end_i", "end_j", "
 # Exported symbols of libga.so, as declared in include/ga.h.
 ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "ga_strerror",
                "ga_pack_words", "ga_pack", "ga_align_batch", "ga_count_cells",
-               "ga_context_set_timing", "ga_context_timing", "ga_pair_class")
+               "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
+               "ga_calibrate_valu")
 
-# Slot counts per lane of the alignment kernels, by class.
-CLASS_SLOTS = (8, 16, 24, 32)
+# Alignment kernels by class: (slots per lane K, waves per pair); class c
+# holds bands of up to 64 * K * waves diagonals.
+CLASSES = ((8, 1), (16, 1), (24, 1), (32, 1), (24, 2), (32, 2), (32, 3), (32, 4))
+CLASS_SLOTS = tuple(k for k, _ in CLASSES)
+MAX_DIAGONALS = 64 * 32 * 4
+
+
+def class_name(c: int) -> str:
+    k, nw = CLASSES[c]
+    return f"ga_dp_kernel<{k},{nw}>"
 
 
 class GaError(RuntimeError):
@@ -68,6 +77,11 @@ def load_library() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname as the system's.
+    # Loading torch first makes libga.so bind to that one runtime; loaded the
+    # other way round, the process would hold two runtimes and torch would
+    # find no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.ga_context_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
@@ -90,6 +104,8 @@ def load_library() -> ctypes.CDLL:
     lib.ga_context_set_timing.restype = ctypes.c_int
     lib.ga_context_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     lib.ga_context_timing.restype = ctypes.c_int
+    lib.ga_calibrate_valu.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.ga_calibrate_valu.restype = ctypes.c_int
     lib.ga_pair_class.argtypes = [i32, i32, i32]
     lib.ga_pair_class.restype = ctypes.c_int
     _lib = lib
@@ -144,10 +160,18 @@ class Context:
         _check(load_library().ga_context_set_timing(self._h, 1 if enable else 0), "ga_context_set_timing")
 
     def timing(self):
-        """Stage milliseconds of the last timed call: [prep, class0..class3]."""
-        ms = (ctypes.c_float * 5)()
-        _check(load_library().ga_context_timing(self._h, ms, 5), "ga_context_timing")
+        """Stage milliseconds of the last timed call: [prep, class 0 .. class 7]."""
+        n = 1 + len(CLASSES)
+        ms = (ctypes.c_float * n)()
+        _check(load_library().ga_context_timing(self._h, ms, n), "ga_context_timing")
         return [float(x) for x in ms]
+
+    def calibrate_valu(self, stream=None) -> float:
+        """Measured int32 VALU lane-ops per second of this device."""
+        v = ctypes.c_double(0.0)
+        _check(load_library().ga_calibrate_valu(self._h, ctypes.byref(v), _stream_handle(stream)),
+               "ga_calibrate_valu")
+        return float(v.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -6,7 +6,8 @@
 // tracking and the z-drop termination test (Eq. 4-7).
 //
 // Kernel shape (differs from the paper's chunked row sweep, Sections 4.1-4.2):
-// one wave64 per pair sweeps the band anti-diagonal by anti-diagonal. Lane l
+// one wave64 per pair (up to 2048 band diagonals; wider bands take 2-4 waves
+// of one workgroup) sweeps the band anti-diagonal by anti-diagonal. Lane l
 // owns K consecutive diagonals d = i - j of the band (slots), kept entirely in
 // VGPRs. Cells of anti-diagonal r lie on diagonals d == r (mod 2), so a step
 // updates one parity class of slots from the other class, which holds
@@ -16,7 +17,9 @@
 // completes a whole anti-diagonal, so the local maximum of Eq. 6 is one wave
 // reduction and the z-drop test of Eq. 5 runs in order with no run-ahead: the
 // rolling window of partial maxima (Section 4.1) and the slice boundary
-// (Section 4.2) are not needed.
+// (Section 4.2) are not needed. With several waves per pair, the waves swap
+// their edge slots and their maxima through LDS once per anti-diagonal,
+// around one workgroup barrier.
 //
 // Boundary cells (row -1 and column -1) are produced by the same recurrence:
 // the slots outside the rectangle start at -inf and the origin at 0, so the
@@ -42,13 +45,26 @@ namespace {
 constexpr int NEG = -(1 << 30);                  // -inf sentinel; range guard keeps it apart
 constexpr int NEG_MAX = -(1 << 30) - (1 << 29);  // below every reachable value
 constexpr int PADB = 64;                         // guard bytes around the unpacked streams
-constexpr int NCLASS = 4;                        // slot counts K = 8, 16, 24, 32 per lane
 constexpr int WAVE = 64;
 
-// Device counters (per call): [0..4) class list sizes, [4..8) class heads.
+// Slot classes: K slots per lane and NW waves per pair hold the band's
+// D <= 64*K*NW diagonals; a pair goes to the first class that holds it.
+constexpr int NCLASS = 8;
+__host__ __device__ constexpr int class_k(int c) { return c == 0 ? 8 : c == 1 ? 16 : (c == 2 || c == 4) ? 24 : 32; }
+__host__ __device__ constexpr int class_nw(int c) { return c < 4 ? 1 : c < 6 ? 2 : c == 6 ? 3 : 4; }
+__host__ __device__ constexpr int class_cap(int c) { return WAVE * class_k(c) * class_nw(c); }
+constexpr int MAX_DIAGONALS = WAVE * 32 * 4;
+
+__host__ __device__ inline int class_of(int64_t D) {
+    for (int c = 0; c < NCLASS; ++c)
+        if (D <= class_cap(c)) return c;
+    return -1;
+}
+
+// Device counters (per call): [0..8) class list sizes, [8..16) class heads.
+// They sit right before the planning histogram in the workspace.
 constexpr int CNT_COUNT = 0;
-constexpr int CNT_HEAD = 4;
-constexpr int CNT_WORDS = 16;
+constexpr int CNT_HEAD = NCLASS;
 
 // Scores are held in a frame that drifts by the piece-1 extension e per
 // anti-diagonal: a value V of a cell on anti-diagonal r is stored as
@@ -87,14 +103,17 @@ __device__ __forceinline__ int dpp_from_upper_lane(int fill, int v) {
     return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xf, 0xf, false);
 }
 
-// Max over the 64 lanes, returned as a wave-uniform value.
+// Max over the 64 lanes, returned as a wave-uniform value. The shifted
+// operand's fill is INT_MIN, the identity of max, so every step folds into
+// one v_max_i32_dpp (rows outside a row_bcast mask keep their value).
 __device__ __forceinline__ int wave_max(int v) {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));   // quad_perm 2,3,0,1
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false));  // row_half_mirror
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false));  // row_mirror
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    constexpr int ID = -2147483647 - 1;
+    v = max(v, __builtin_amdgcn_update_dpp(ID, v, 0xB1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
+    v = max(v, __builtin_amdgcn_update_dpp(ID, v, 0x4E, 0xf, 0xf, false));   // quad_perm 2,3,0,1
+    v = max(v, __builtin_amdgcn_update_dpp(ID, v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(ID, v, 0x140, 0xf, 0xf, false));  // row_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(ID, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(ID, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
     return __builtin_amdgcn_readlane(v, 63);
 }
 
@@ -168,18 +187,22 @@ __device__ __forceinline__ void update_class(PairState<K> &st, const DpArgs &P, 
 }
 
 // Update the slots of parity class C with cell index KC (0..3) of the block.
+// f0..f2 enter at the pair's outer lane edge: lane 0's lower neighbour (A, E,
+// X) for class 0, lane 63's upper neighbour (A, F, Y) for class 1. They are
+// -inf at a band edge and the neighbouring wave's edge values inside a
+// multi-wave pair.
 template <int K, int C, int KC>
-__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P) {
+__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, int f0, int f1, int f2) {
     int ae = 0, ee = 0, xe = 0;  // class 0: slot -1 = lower lane's slot K-1 (up)
     int af = 0, ff = 0, yf = 0;  // class 1: slot K = upper lane's slot 0 (left)
     if (C == 0) {
-        ae = dpp_from_lower_lane(NEG, st.A[K - 1]);
-        ee = dpp_from_lower_lane(NEG, st.E[K - 1]);
-        xe = dpp_from_lower_lane(NEG, st.X[K - 1]);
+        ae = dpp_from_lower_lane(f0, st.A[K - 1]);
+        ee = dpp_from_lower_lane(f1, st.E[K - 1]);
+        xe = dpp_from_lower_lane(f2, st.X[K - 1]);
     } else {
-        af = dpp_from_upper_lane(NEG, st.A[0]);
-        ff = dpp_from_upper_lane(NEG, st.F[0]);
-        yf = dpp_from_upper_lane(NEG, st.Y[0]);
+        af = dpp_from_upper_lane(f0, st.A[0]);
+        ff = dpp_from_upper_lane(f1, st.F[0]);
+        yf = dpp_from_upper_lane(f2, st.Y[0]);
     }
     // piece-2 openings of the other class, shared by both neighbours
     int B[K];
@@ -207,6 +230,7 @@ __device__ __forceinline__ void clamp_wall(PairState<K> &st, uint64_t wall_lanes
 struct Geo {
     int n, m;
     int a0;        // lowest diagonal held (band edge, or -m: the boundary row)
+    int a0w;       // the first diagonal of this wave's slots (a0 for wave 0)
     int dlo, dhi;  // diagonals with interior cells
     int r_last;    // last non-empty anti-diagonal
     int fast_lo, fast_hi;  // anti-diagonals on which every held slot is interior
@@ -217,12 +241,31 @@ struct Track {
     int G, gi, gj;        // global maximum (Eq. 7); gi/gj valid once resolved
     int endS, endI, endJ; // local maximum where the sweep ended
     int zd;
-    // where G was taken, kept lazily: the anti-diagonal, the lane holding
-    // the cell, the slot class and the frame value; that lane's class values
-    // are parked in LDS until the cell is needed
-    int g_r, g_lane, g_cls, g_ma;
-    bool g_open;
+    // where G was taken, kept lazily: the anti-diagonal, the wave holding
+    // the cell, the slot class and the frame value; the holding wave parks
+    // that class's values in LDS until the cell is needed
+    int g_r, g_wave, g_cls, g_ma;
+    bool g_open;  // G moved since its cell was last resolved
+    bool g_set;   // G has moved off the origin
+    bool stop;    // (several waves) this wave found the z-drop: tell the others
 };
+
+// LDS of one pair's workgroup: the park of the wave holding the global
+// maximum (slot-major, so 64 lanes write 64 consecutive words), and with
+// several waves per pair the per-anti-diagonal exchange, double buffered by
+// anti-diagonal parity: the edge values each wave publishes for its
+// neighbour's next step and each wave's maximum.
+template <int K, int NW>
+struct PairLds {
+    int park[K * WAVE];  // park[s * 64 + lane] = A of slot s
+    int edge[2][NW][3];
+    int ma[2][NW];
+    int idx;             // pair index handed to every wave
+};
+
+// A wave maximum no cell can take: a wave publishes it in place of its
+// maximum to tell the others that the sweep has ended.
+constexpr int STOP = -2147483647 - 1;
 
 // Interior diagonals of anti-diagonal r, clipped to its parity.
 __device__ __forceinline__ void diag_window(const Geo &g, int r, int &vlo, int &vhi) {
@@ -234,13 +277,13 @@ __device__ __forceinline__ void diag_window(const Geo &g, int r, int &vlo, int &
 
 // Smallest-i cell attaining the frame value MA among the class-C slots of
 // anti-diagonal r whose diagonals lie in [vlo, vhi] (lowest lane first, then
-// lowest slot: i grows with the diagonal).
+// lowest slot: i grows with the diagonal). Called by the wave holding MA.
 template <int K, int C>
 __device__ __forceinline__ void locate(const PairState<K> &st, const Geo &g, int lm, int MA, int r,
                                        int vlo, int vhi, int &mi, int &mj) {
     const uint64_t bal = __ballot(lm == MA);
     const int L = __builtin_ctzll(bal);
-    const int dL = g.a0 + L * K;
+    const int dL = g.a0w + L * K;
     int found = C;
 #pragma unroll
     for (int s = K - 2 + C; s >= C; s -= 2) {
@@ -252,64 +295,100 @@ __device__ __forceinline__ void locate(const PairState<K> &st, const Geo &g, int
     mj = (r - dm) >> 1;
 }
 
-// The cell of the global maximum from the values parked in LDS.
-template <int K>
-__device__ __forceinline__ void resolve_g(Track &tr, const Geo &g, const int *park, int lane) {
-    if (!tr.g_open) return;
+// The cell of the global maximum, from the values its wave parked: the
+// lowest (lane, slot) of class g_cls holding g_ma on an interior diagonal of
+// anti-diagonal g_r. Any wave of the pair can run it once the park is
+// visible to it.
+template <int K, int NW>
+__device__ __forceinline__ void park_cell(const Track &tr, const Geo &g, const PairLds<K, NW> &S, int lane,
+                                          int &gi, int &gj) {
     int vlo, vhi;
     diag_window(g, tr.g_r, vlo, vhi);
-    const int dL = g.a0 + tr.g_lane * K + tr.g_cls;
-    const int t = lane < K / 2 ? lane : 0;
-    const int d = dL + 2 * t;
-    const bool hit = lane < K / 2 && park[t] == tr.g_ma && d >= vlo && d <= vhi;
-    const int first = __builtin_ctzll(__ballot(hit));
-    const int dm = dL + 2 * first;
-    tr.gi = (tr.g_r + dm) >> 1;
-    tr.gj = (tr.g_r - dm) >> 1;
-    tr.g_open = false;
+    const int dl = g.a0 + (tr.g_wave * WAVE + lane) * K + tr.g_cls;  // this lane's first class slot
+    int hit = K;
+#pragma unroll
+    for (int t = K / 2 - 1; t >= 0; --t) {
+        const int v = S.park[(tr.g_cls + 2 * t) * WAVE + lane];
+        const int d = dl + 2 * t;
+        if (v == tr.g_ma && d >= vlo && d <= vhi) hit = t;
+    }
+    const int L = __builtin_ctzll(__ballot(hit < K));
+    const int t = __builtin_amdgcn_readlane(hit, L);
+    const int dm = g.a0 + (tr.g_wave * WAVE + L) * K + tr.g_cls + 2 * t;
+    gi = (tr.g_r + dm) >> 1;
+    gj = (tr.g_r - dm) >> 1;
 }
 
-// After the class-C update of anti-diagonal r: local maximum (Eq. 6), global
-// maximum (Eq. 7) and the z-drop test (Eq. 5). Returns true when done.
-template <int K, int C>
-__device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &P, const Geo &g,
-                                          Track &tr, int r, int lane, bool masked, int *park) {
-    int vlo = 0, vhi = 0;
+// New global maximum: the wave holding it parks the class-C values of all
+// its lanes (no lane selection on the hot path; the cell is found lazily).
+template <int K, int C, int NW>
+__device__ __forceinline__ void park_class(const PairState<K> &st, PairLds<K, NW> &S, int lane) {
+#pragma unroll
+    for (int s = C; s < K; s += 2) S.park[s * WAVE + lane] = st.A[s];
+}
+
+// This wave's lane maximum of the class-C slots of anti-diagonal r over the
+// interior diagonals [vlo, vhi] (masked), or over every slot (the band is
+// interior on this anti-diagonal). NEG_MAX when the wave holds none.
+template <int K, int C, int NW>
+__device__ __forceinline__ int lane_max(const PairState<K> &st, const Geo &g, int vlo, int vhi, bool masked) {
     int lm = NEG_MAX;
     if (masked) {
-        diag_window(g, r, vlo, vhi);
-        if (vlo > vhi) return r >= g.r_last;  // no interior cell: nothing to test
-        // lanes holding slot s inside [vlo, vhi]: a lane range per slot
-        const int u = vlo - g.a0, v = vhi - g.a0;
-        const int qu = u / K, ru = u % K, qv = v / K, rv = v % K;
-        const uint64_t lo0 = lanes_from(qu), lo1 = lanes_from(qu + 1);
-        const uint64_t hi0 = lanes_upto(qv), hi1 = lanes_upto(qv - 1);
-        const int negmax = NEG_MAX;
+        // this wave's slots inside [vlo, vhi]: a lane range per slot
+        // (one wave: [vlo, vhi] lies inside the held band, so no clipping)
+        const int u = NW == 1 ? vlo - g.a0w : max(vlo - g.a0w, 0);
+        const int v = NW == 1 ? vhi - g.a0w : min(vhi - g.a0w, WAVE * K - 1);
+        if (NW == 1 || u <= v) {
+            const int qu = u / K, ru = u % K, qv = v / K, rv = v % K;
+            const uint64_t lo0 = lanes_from(qu), lo1 = lanes_from(qu + 1);
+            const uint64_t hi0 = lanes_upto(qv), hi1 = lanes_upto(qv - 1);
+            const int negmax = NEG_MAX;
 #pragma unroll
-        for (int s = C; s < K; s += 2) {
-            const uint64_t msk = (ru > s ? lo1 : lo0) & (rv >= s ? hi0 : hi1);
-            lm = max(lm, select_by_lanes(msk, st.A[s], negmax));
+            for (int s = C; s < K; s += 2) {
+                const uint64_t msk = (ru > s ? lo1 : lo0) & (rv >= s ? hi0 : hi1);
+                lm = max(lm, select_by_lanes(msk, st.A[s], negmax));
+            }
         }
     } else {
 #pragma unroll
         for (int s = C; s < K; s += 2) lm = max(lm, st.A[s]);
     }
+    return lm;
+}
+
+// One wave per pair, after the class-C update of anti-diagonal r: local
+// maximum (Eq. 6), global maximum (Eq. 7) and the z-drop test (Eq. 5).
+// Returns true when done.
+template <int K, int C>
+__device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &P, const Geo &g,
+                                          Track &tr, int r, int lane, bool masked, PairLds<K, 1> &S) {
+    int vlo = 0, vhi = 0;
+    if (masked) {
+        diag_window(g, r, vlo, vhi);
+        if (vlo > vhi) return r >= g.r_last;  // no interior cell: nothing to test
+    }
+    const int lm = lane_max<K, C, 1>(st, g, vlo, vhi, masked);
+    const bool last = r >= g.r_last;
+    if (!last) {
+        // the wave reduction only matters if some lane is above G (a new
+        // maximum) or every lane is more than Z below it (a z-drop
+        // candidate); two compares settle that for most anti-diagonals
+        const int gF = tr.G - P.q1 + P.e1 * r;  // G in this anti-diagonal's frame
+        const bool up = __ballot(lm > gF) != 0;
+        const bool low = P.Z >= 0 && __ballot(lm >= gF - P.Z) == 0;
+        if (__builtin_expect(!up && !low, 1)) return false;
+    }
     const int MA = wave_max(lm);
     const int M = MA + P.q1 - P.e1 * r;  // back to the true score
-    const bool last = r >= g.r_last;
     if (M > tr.G) {
-        // new global maximum: park the holding lane's class values
-        const int L = __builtin_ctzll(__ballot(lm == MA));
-        if (lane == L) {
-#pragma unroll
-            for (int s = C; s < K; s += 2) park[s >> 1] = st.A[s];
-        }
+        park_class<K, C, 1>(st, S, lane);
         tr.G = M;
         tr.g_r = r;
-        tr.g_lane = L;
+        tr.g_wave = 0;
         tr.g_cls = C;
         tr.g_ma = MA;
         tr.g_open = true;
+        tr.g_set = true;
         if (last) {
             if (!masked) diag_window(g, r, vlo, vhi);
             locate<K, C>(st, g, lm, MA, r, vlo, vhi, tr.endI, tr.endJ);
@@ -325,7 +404,10 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
         tr.endI = mi;
         tr.endJ = mj;
         if (P.Z >= 0 && tr.G - M > P.Z) {
-            resolve_g<K>(tr, g, park, lane);
+            if (tr.g_open) {
+                park_cell<K, 1>(tr, g, S, lane, tr.gi, tr.gj);
+                tr.g_open = false;
+            }
             if (mi > tr.gi && mj > tr.gj) {
                 int dd = (mi - tr.gi) - (mj - tr.gj);
                 dd = dd < 0 ? -dd : dd;
@@ -339,19 +421,147 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
     return last;
 }
 
-template <int K>
+// Several waves per pair, after the class-C update of anti-diagonal r. One
+// barrier per anti-diagonal: each wave publishes its maximum, then all read
+// every wave's maximum and take the same decisions from the same values.
+// The rare events that need a cell (the last anti-diagonal, a z-drop
+// candidate) are handled by the wave holding the anti-diagonal maximum
+// alone: it resolves the cells, runs the test, writes the pair's result and,
+// on a z-drop, publishes STOP in place of its maximum at the next
+// anti-diagonal, where every wave then stops (the extra anti-diagonal they
+// computed is never looked at). Returns true when done.
+template <int K, int C, int NW>
+__device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArgs &P, const Geo &g,
+                                             Track &tr, int r, int lane, int wv, bool masked,
+                                             PairLds<K, NW> &S, int p) {
+    int vlo = 0, vhi = 0;
+    bool any = true;  // the anti-diagonal has interior cells
+    if (masked) {
+        diag_window(g, r, vlo, vhi);
+        any = vlo <= vhi;
+    }
+    const int lm = any ? lane_max<K, C, NW>(st, g, vlo, vhi, masked) : NEG_MAX;
+    const int MAw = wave_max(lm);
+    const int b = r & 1;
+    if (lane == 0) S.ma[b][wv] = tr.stop ? STOP : MAw;
+    __syncthreads();
+    // LDS loads land in VGPRs: readfirstlane keeps the decisions scalar
+    int MA = __builtin_amdgcn_readfirstlane(S.ma[b][0]);
+    int vstar = 0;  // lowest wave holding MA: the smallest diagonal, hence the smallest i
+    bool stop = MA == STOP;
+#pragma unroll
+    for (int k = 1; k < NW; ++k) {
+        const int x = __builtin_amdgcn_readfirstlane(S.ma[b][k]);
+        stop = stop || x == STOP;
+        if (x > MA) {
+            MA = x;
+            vstar = k;
+        }
+    }
+    if (stop) return true;
+    const bool last = r >= g.r_last;
+    if (!any) return last;
+    const int M = MA + P.q1 - P.e1 * r;  // back to the true score
+    const bool up = M > tr.G;
+    if (up) {
+        if (wv == vstar) park_class<K, C, NW>(st, S, lane);
+        tr.G = M;
+        tr.g_r = r;
+        tr.g_wave = vstar;
+        tr.g_cls = C;
+        tr.g_ma = MA;
+        tr.g_set = true;
+    }
+    const bool cand = !up && P.Z >= 0 && tr.G - M > P.Z;
+    if (!(cand || last)) return false;
+    if (wv == vstar) {
+        if (!masked) diag_window(g, r, vlo, vhi);
+        int mi, mj, gi = -1, gj = -1;
+        locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
+        if (up) {
+            gi = mi;
+            gj = mj;
+        } else if (tr.g_set) {
+            park_cell<K, NW>(tr, g, S, lane, gi, gj);
+        }
+        bool drop = false;
+        if (cand && mi > gi && mj > gj) {
+            int dd = (mi - gi) - (mj - gj);
+            dd = dd < 0 ? -dd : dd;
+            drop = tr.G - M > P.Z + P.e2 * dd;
+        }
+        if (drop || last) {
+            if (lane < 7) {
+                const int v[7] = {tr.G, gi, gj, M, mi, mj, drop ? 1 : 0};
+                int val = v[0];
+#pragma unroll
+                for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
+                reinterpret_cast<int32_t *>(P.out + p)[lane] = val;
+            }
+            tr.stop = drop;
+        }
+    }
+    return last;
+}
+
+// Several waves per pair: after the class-C update of anti-diagonal r, publish
+// the edge values the neighbouring wave needs for anti-diagonal r+1 ...
+template <int K, int C, int NW>
+__device__ __forceinline__ void publish_edges(const PairState<K> &st, PairLds<K, NW> &S, int r, int lane,
+                                              int wv) {
+    const int b = r & 1;
+    if (C == 1) {  // slot K-1 of lane 63 is the upper wave's "up" neighbour
+        if (wv < NW - 1 && lane == WAVE - 1) {
+            S.edge[b][wv][0] = st.A[K - 1];
+            S.edge[b][wv][1] = st.E[K - 1];
+            S.edge[b][wv][2] = st.X[K - 1];
+        }
+    } else {  // slot 0 of lane 0 is the lower wave's "left" neighbour
+        if (wv > 0 && lane == 0) {
+            S.edge[b][wv][0] = st.A[0];
+            S.edge[b][wv][1] = st.F[0];
+            S.edge[b][wv][2] = st.Y[0];
+        }
+    }
+}
+
+// ... and read them at the start of the class-C update of anti-diagonal r.
+template <int C, int K, int NW>
+__device__ __forceinline__ void read_edges(const PairLds<K, NW> &S, int r, int wv, int &f0, int &f1,
+                                           int &f2) {
+    f0 = f1 = f2 = NEG;
+    if constexpr (NW > 1) {
+        const int b = (r - 1) & 1;
+        const int src = C == 0 ? wv - 1 : wv + 1;
+        if (src >= 0 && src < NW) {
+            f0 = S.edge[b][src][0];
+            f1 = S.edge[b][src][1];
+            f2 = S.edge[b][src][2];
+        }
+    }
+}
+
+template <int K, int NW>
 __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
-                                          Track &tr, int r0, int lane, uint64_t wall_lanes,
-                                          int wall_pos, bool masked, int *park) {
+                                          Track &tr, int r0, int lane, int wv, uint64_t wall_lanes,
+                                          int wall_pos, bool masked, PairLds<K, NW> &S, int p) {
 #define GA_STEP(T)                                                                    \
     {                                                                                 \
         constexpr int C = (T) & 1;                                                    \
         constexpr int KC = (T) >> 1;                                                  \
         const int r = r0 + (T);                                                       \
         if (r >= 0) {                                                                 \
-            dp_step<K, C, KC>(st, P);                                                 \
+            int f0, f1, f2;                                                           \
+            read_edges<C, K, NW>(S, r, wv, f0, f1, f2);                               \
+            dp_step<K, C, KC>(st, P, f0, f1, f2);                                     \
             if (wall_lanes != 0 && (wall_pos & 1) == C) clamp_wall<K>(st, wall_lanes, wall_pos); \
-            if (post_step<K, C>(st, P, g, tr, r, lane, masked, park)) return true;   \
+            if constexpr (NW > 1) publish_edges<K, C, NW>(st, S, r, lane, wv);        \
+            if constexpr (NW == 1) {                                                  \
+                if (post_step<K, C>(st, P, g, tr, r, lane, masked, S)) return true;   \
+            } else {                                                                  \
+                if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, masked, S, p))  \
+                    return true;                                                      \
+            }                                                                         \
         }                                                                             \
     }
     GA_STEP(0)
@@ -395,6 +605,11 @@ __device__ __forceinline__ void load_windows(Windows<K> &wd, const uint8_t *tbas
     wd.qo = qs & 3;
 }
 
+// v_bitop3 truth table of (x, y, m) -> m ? (x | y) : (x ^ y), built the way
+// the instruction indexes it: operand bits (x, y, m) form the index with x as
+// the most significant bit, i.e. the table is f applied to 0xF0, 0xCC, 0xAA.
+constexpr uint32_t CLS_TT = (((0xF0u | 0xCCu) & 0xAAu) | ((0xF0u ^ 0xCCu) & ~0xAAu)) & 0xFFu;
+
 template <int K>
 __device__ __forceinline__ void build_scores(PairState<K> &st, const Windows<K> &wd, const DpArgs &P) {
     constexpr int KH = K / 2;
@@ -410,13 +625,15 @@ __device__ __forceinline__ void build_scores(PairState<K> &st, const Windows<K> 
         const int c = s & 1, sp = s >> 1;
         const uint32_t t4 = window4(TW, c + sp);       // T[I0+c+sp .. +4)
         const uint32_t q4 = window4(QW, KH - 1 - sp);  // Q[J0-sp .. +4)
-        const uint32_t cls = (t4 ^ q4) | ((t4 | q4) & 0x04040404u);
+        // class byte: t ^ q in bits 0-1, (t | q) & 4 (either is N) in bit 2,
+        // one v_bitop3 with the bit-2 mask as third operand
+        const uint32_t cls = __builtin_amdgcn_bitop3_b32(t4, q4, 0x04040404u, CLS_TT);
         st.S4[s] = __builtin_amdgcn_perm(P.lut_hi, P.lut_lo, cls);
     }
 }
 
-template <int K>
-__device__ void align_pair(const DpArgs &P, int p, int lane, int *park) {
+template <int K, int NW>
+__device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, NW> &S) {
     Geo g;
     g.n = P.t_len[p];
     g.m = P.q_len[p];
@@ -429,6 +646,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int *park) {
         g.a0 = -m;
         a1 = n;
     }
+    g.a0w = g.a0 + wv * (WAVE * K);
     g.dlo = max(g.a0, 1 - m);
     g.dhi = min(a1, n - 1);
     const int D = a1 - g.a0 + 1;
@@ -440,11 +658,13 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int *park) {
     g.fast_ok = (g.a0 == g.dlo) && (a1 == g.dhi) && (g.dhi > g.dlo);
     g.fast_lo = max(-g.dlo, g.dhi);
     g.fast_hi = min(2 * m - 2 + g.dlo, 2 * n - 2 - g.dhi);
-    const bool has_wall = D < WAVE * K;
-    const int wall_pos = D % K;
-    const uint64_t wall_lanes = has_wall ? (1ull << (D / K)) : 0ull;
+    // the right wall: array position D, in this wave or not
+    const int Dw = D - wv * (WAVE * K);
+    const bool has_wall = Dw >= 0 && Dw < WAVE * K;
+    const int wall_pos = has_wall ? Dw % K : 0;
+    const uint64_t wall_lanes = has_wall ? (1ull << (Dw / K)) : 0ull;
 
-    const int d0 = g.a0 + lane * K;
+    const int d0 = g.a0w + lane * K;
     PairState<K> st;
     {
         // boundary values in the frame: origin (-1,-1) on anti-diagonal -2,
@@ -474,30 +694,42 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int *park) {
             }
         }
     }
-    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false};
+    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false, false};
 
     const uint8_t *tbase = P.tb + 16 * P.t_off[p];
     const uint8_t *qbase = P.qb + 16 * P.q_off[p];
     // blocks of 8 anti-diagonals, each starting on the class of slot 0
     int r0 = (g.a0 & 1) ? -1 : -2;
+    if constexpr (NW > 1) {
+        // the edges of anti-diagonal -1 for the first step (anti-diagonal 0,
+        // class 2 + r0, i.e. 0 when r0 = -2 and 1 when r0 = -1)
+        if (r0 == -2)
+            publish_edges<K, 1, NW>(st, S, -1, lane, wv);
+        else
+            publish_edges<K, 0, NW>(st, S, -1, lane, wv);
+        __syncthreads();
+    }
     Windows<K> wd;
     load_windows<K>(wd, tbase, qbase, n, m, r0, d0);
     for (;;) {
         build_scores<K>(st, wd, P);
         load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, d0);  // next block, in flight
         const bool fast = g.fast_ok && r0 >= g.fast_lo && r0 + 7 <= g.fast_hi;
-        const bool done = run_block<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, !fast, park);
+        const bool done = run_block<K, NW>(st, P, g, tr, r0, lane, wv, wall_lanes, wall_pos, !fast, S, p);
         if (done) break;
         r0 += 8;
     }
-    resolve_g<K>(tr, g, park, lane);
-    if (lane < 7) {
-        const int v[7] = {tr.G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
-        int val = v[0];
+    if constexpr (NW == 1) {
+        if (tr.g_open) park_cell<K, 1>(tr, g, S, lane, tr.gi, tr.gj);
+        if (lane < 7) {
+            const int v[7] = {tr.G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
+            int val = v[0];
 #pragma unroll
-        for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
-        reinterpret_cast<int32_t *>(P.out + p)[lane] = val;
+            for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
+            reinterpret_cast<int32_t *>(P.out + p)[lane] = val;
+        }
     }
+    // (several waves: the wave that ended the sweep has written the result)
 }
 
 // Waves per SIMD each slot count is compiled for (register budget).
@@ -506,19 +738,54 @@ struct Occ {
     static constexpr int value = K <= 8 ? 4 : (K <= 16 ? 3 : 2);
 };
 
-template <int K>
-__global__ __launch_bounds__(64, Occ<K>::value) void ga_dp_kernel(DpArgs P) {
-    __shared__ int park[K / 2];  // class values of the lane that holds the global maximum
-    const int lane = threadIdx.x;
+// Persistent kernel: each workgroup of NW waves takes pairs of its class from
+// the cost-ordered list through an atomic head until the list is exhausted.
+template <int K, int NW>
+__global__ __launch_bounds__(WAVE * NW, Occ<K>::value) void ga_dp_kernel(DpArgs P) {
+    __shared__ PairLds<K, NW> S;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int count = P.counters[CNT_COUNT + P.cls];
     for (;;) {
         int idx = 0;
-        if (lane == 0) idx = atomicAdd(&P.counters[CNT_HEAD + P.cls], 1);
-        idx = __builtin_amdgcn_readfirstlane(idx);
+        if constexpr (NW == 1) {
+            if (lane == 0) idx = atomicAdd(&P.counters[CNT_HEAD + P.cls], 1);
+            idx = __builtin_amdgcn_readfirstlane(idx);
+        } else {
+            if (threadIdx.x == 0) S.idx = atomicAdd(&P.counters[CNT_HEAD + P.cls], 1);
+            __syncthreads();
+            idx = __builtin_amdgcn_readfirstlane(S.idx);
+            __syncthreads();  // every wave has read S.idx before the next pair overwrites it
+        }
         if (idx >= count) break;
         const int p = P.list[idx];
-        align_pair<K>(P, p, lane, park);
+        align_pair<K, NW>(P, p, lane, wv, S);
     }
+}
+
+// Integer VALU peak probe: every lane runs CAL_CHAINS independent chains of
+// v_max3_i32 / v_add_u32 pairs (inline asm, so nothing folds), enough
+// independent work per wave to hide issue latency. One lane-op per
+// instruction per lane.
+constexpr int CAL_CHAINS = 8;
+constexpr int CAL_WAVES_PER_SIMD = 8;
+
+__global__ __launch_bounds__(256) void ga_valu_probe(int32_t iters, int32_t *sink) {
+    int a[CAL_CHAINS];
+#pragma unroll
+    for (int k = 0; k < CAL_CHAINS; ++k) a[k] = (int)threadIdx.x + k;
+    const int x = (int)blockIdx.x, y = -(int)threadIdx.x;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < CAL_CHAINS; ++k) {
+            asm volatile("v_max3_i32 %0, %0, %1, %2" : "+v"(a[k]) : "v"(x), "v"(y));
+            asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[k]) : "v"(x));
+        }
+    }
+    int acc = 0;
+#pragma unroll
+    for (int k = 0; k < CAL_CHAINS; ++k) acc ^= a[k];
+    if (acc == 0x7fffffff) sink[0] = acc;  // keeps the chains live; practically never stores
 }
 
 __global__ void ga_zero_i32(int32_t *x, int64_t n) {
@@ -557,6 +824,16 @@ __global__ void ga_unpack(const uint32_t *words, const uint32_t *nmask, int64_t 
     }
 }
 
+// Work planning. A wave's time on a pair is proportional to the number of
+// anti-diagonals it sweeps, whatever the band's occupancy, so pairs are
+// ordered by n + m, longest first, within each slot class: the persistent
+// waves then finish on short pairs instead of waiting on one long straggler.
+// Counting sort over cost buckets of PLAN_SHIFT anti-diagonals: classify and
+// histogram, an exclusive scan in descending bucket order, then a scatter.
+constexpr int PLAN_BUCKETS = 4096;  // per class; the last bucket takes every longer pair
+constexpr int PLAN_SHIFT = 5;
+constexpr int PLAN_BINS = NCLASS * PLAN_BUCKETS;
+
 struct PlanArgs {
     int64_t n_pairs;
     const int64_t *t_off, *q_off;
@@ -565,46 +842,95 @@ struct PlanArgs {
     int32_t max_len;
     int32_t w;
     int32_t *counters;
-    int32_t *lists;  // NCLASS lists of n_pairs entries
+    int32_t *hist;    // [PLAN_BINS] pairs per (class, bucket)
+    int32_t *cursor;  // [PLAN_BINS] next list position per (class, bucket)
+    int32_t *keys;    // [n_pairs] class * PLAN_BUCKETS + bucket, or -1 when finished here
+    int32_t *lists;   // NCLASS lists of n_pairs entries
     int32_t *err;
     ga_result_t *out;
 };
 
-// Validate each pair, finish empty pairs, and append the rest to the work
-// list of the smallest slot count that holds the pair's diagonals.
-__global__ void ga_plan(PlanArgs A) {
+// Validate each pair, finish invalid and empty pairs, and give the rest a
+// (slot class, cost bucket) key: the class is the smallest slot count that
+// holds the pair's diagonals.
+__global__ void ga_plan_classify(PlanArgs A) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= A.n_pairs) return;
     const int32_t n = A.t_len[p], m = A.q_len[p];
     const int64_t to = A.t_off[p], qo = A.q_off[p];
     const bool bad = n < 0 || m < 0 || n > A.max_len || m > A.max_len || to < 0 || qo < 0 ||
                      to + (n + 15) / 16 > A.t_nwords || qo + (m + 15) / 16 > A.q_nwords;
+    int key = -1;
     if (bad) {
         atomicOr(A.err, 1);
         A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
-        return;
-    }
-    if (n == 0 || m == 0) {
+    } else if (n == 0 || m == 0) {
         A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, 0};
-        return;
-    }
-    int a0, a1;
-    if (A.w >= 0) {
-        a0 = max(-A.w, -m);
-        a1 = min(A.w, n);
     } else {
-        a0 = -m;
-        a1 = n;
+        int a0, a1;
+        if (A.w >= 0) {
+            a0 = max(-A.w, -m);
+            a1 = min(A.w, n);
+        } else {
+            a0 = -m;
+            a1 = n;
+        }
+        const int D = a1 - a0 + 1;
+        const int cls = class_of(D);
+        if (cls < 0) {
+            atomicOr(A.err, 2);
+            A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
+        } else {
+            const int bucket = min((n + m) >> PLAN_SHIFT, PLAN_BUCKETS - 1);
+            key = cls * PLAN_BUCKETS + bucket;
+            atomicAdd(&A.hist[key], 1);
+        }
     }
-    const int D = a1 - a0 + 1;
-    const int cls = (D + 511) / 512 - 1;
-    if (cls >= NCLASS) {
-        atomicOr(A.err, 2);
-        A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
-        return;
+    A.keys[p] = key;
+}
+
+// One workgroup of 1024 threads: per class, list positions of the buckets in
+// descending cost order (exclusive scan), and the class list sizes.
+__global__ __launch_bounds__(1024) void ga_plan_scan(PlanArgs A) {
+    constexpr int PER = PLAN_BUCKETS / 1024;  // buckets per thread, in descending order
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    for (int c = 0; c < NCLASS; ++c) {
+        const int *h = A.hist + c * PLAN_BUCKETS;
+        // thread t owns descending ranks t*PER .. t*PER+PER-1, i.e. buckets B-1-rank
+        int v[PER], sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            v[k] = h[PLAN_BUCKETS - 1 - (t * PER + k)];
+            sum += v[k];
+        }
+        part[t] = sum;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int x = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += x;
+            __syncthreads();
+        }
+        int run = part[t] - sum;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            A.cursor[c * PLAN_BUCKETS + PLAN_BUCKETS - 1 - (t * PER + k)] = run;
+            run += v[k];
+        }
+        if (t == 1023) A.counters[CNT_COUNT + c] = part[1023];
+        __syncthreads();
     }
-    const int idx = atomicAdd(&A.counters[CNT_COUNT + cls], 1);
-    A.lists[cls * A.n_pairs + idx] = (int32_t)p;
+}
+
+__global__ void ga_plan_scatter(PlanArgs A) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= A.n_pairs) return;
+    const int key = A.keys[p];
+    if (key < 0) return;
+    const int cls = key / PLAN_BUCKETS;
+    const int pos = atomicAdd(&A.cursor[key], 1);
+    A.lists[cls * A.n_pairs + pos] = (int32_t)p;
 }
 
 // ---- packing: ASCII -> 2-bit stream + N bitmap (input packing, Section 2.2)
@@ -686,6 +1012,7 @@ constexpr int NEVENTS = 2 + NCLASS;
 struct ga_context {
     int device;
     int num_cu;
+    int blocks_per_cu[NCLASS];  // resident workgroups of each slot class's kernel per CU
     void *ws;          // workspace
     size_t ws_size;
     int32_t *d_err;    // device error latch
@@ -726,9 +1053,19 @@ struct SetDevice {
     }
 };
 
-template <int K>
+template <int K, int NW>
 void launch_dp(const DpArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(ga_dp_kernel<K>, dim3(grid), dim3(WAVE), 0, s, a);
+    hipLaunchKernelGGL((ga_dp_kernel<K, NW>), dim3(grid), dim3(WAVE * NW), 0, s, a);
+}
+
+template <int K, int NW>
+int blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ga_dp_kernel<K, NW>, WAVE * NW, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        nb = 0;
+    }
+    return nb > 0 ? nb : 1;
 }
 
 }  // namespace
@@ -761,6 +1098,15 @@ int ga_context_create(ga_context_t **out, int device) {
     ctx->device = device;
     if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         ctx->num_cu = 256;
+    // persistent grids: as many workgroups as the registers let reside
+    ctx->blocks_per_cu[0] = blocks_per_cu<8, 1>();
+    ctx->blocks_per_cu[1] = blocks_per_cu<16, 1>();
+    ctx->blocks_per_cu[2] = blocks_per_cu<24, 1>();
+    ctx->blocks_per_cu[3] = blocks_per_cu<32, 1>();
+    ctx->blocks_per_cu[4] = blocks_per_cu<24, 2>();
+    ctx->blocks_per_cu[5] = blocks_per_cu<32, 2>();
+    ctx->blocks_per_cu[6] = blocks_per_cu<32, 3>();
+    ctx->blocks_per_cu[7] = blocks_per_cu<32, 4>();
     if (hipMalloc(&ctx->d_err, sizeof(int32_t)) != hipSuccess) {
         (void)hipGetLastError();
         free(ctx);
@@ -835,9 +1181,7 @@ int ga_pair_class(int32_t n, int32_t m, int32_t w) {
         a0 = -m;
         a1 = n;
     }
-    const int64_t D = a1 - a0 + 1;
-    const int64_t cls = (D + 511) / 512 - 1;
-    return cls < NCLASS ? (int)cls : -1;
+    return class_of(a1 - a0 + 1);
 }
 
 int64_t ga_pack_words(const int32_t *len_host, int64_t n) {
@@ -870,6 +1214,36 @@ int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
     hipLaunchKernelGGL(ga_pack_kernel, dim3((unsigned)n), dim3(64), 0, s, ascii_dev, off_dev, len_dev,
                        word_off_dev, nwords, words_dev, nmask_dev, ctx->d_err);
     return hipGetLastError() == hipSuccess ? GA_OK : GA_EHIP;
+}
+
+int ga_calibrate_valu(ga_context_t *ctx, double *lane_ops_per_s, void *stream) {
+    if (!ctx || !lane_ops_per_s) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_ws(ctx, 256);
+    if (rc != GA_OK) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return GA_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return GA_EHIP;
+    }
+    const int threads = 256;  // 4 waves per workgroup
+    const int blocks = ctx->num_cu * 4 * CAL_WAVES_PER_SIMD / (threads / WAVE);
+    const int iters = 20000;
+    int32_t *sink = (int32_t *)ctx->ws;
+    hipLaunchKernelGGL(ga_valu_probe, dim3(blocks), dim3(threads), 0, s, 100, sink);  // warm up
+    hipEventRecord(e0, s);
+    hipLaunchKernelGGL(ga_valu_probe, dim3(blocks), dim3(threads), 0, s, iters, sink);
+    hipEventRecord(e1, s);
+    float ms = 0.f;
+    const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!ok || ms <= 0.f) return GA_EHIP;
+    const double ops = (double)blocks * threads * iters * CAL_CHAINS * 2;
+    *lane_ops_per_s = ops / (ms * 1e-3);
+    return GA_OK;
 }
 
 int64_t ga_count_cells(int32_t n, int32_t m, int32_t w, int32_t r_end) {
@@ -917,13 +1291,16 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     }
     {
         const int64_t wl = w < 0 ? bt->max_len : (w < bt->max_len ? w : bt->max_len);
-        if (2 * wl + 1 > 64 * 32) return GA_EUNSUPPORTED;
+        if (2 * wl + 1 > MAX_DIAGONALS) return GA_EUNSUPPORTED;
     }
     SetDevice sd(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     const int64_t np = bt->n_pairs;
     const size_t off_cnt = 0;
-    const size_t off_lists = 256;
+    const size_t off_hist = 256;
+    const size_t off_cursor = off_hist + sizeof(int32_t) * PLAN_BINS;
+    const size_t off_keys = off_cursor + sizeof(int32_t) * PLAN_BINS;
+    const size_t off_lists = align_up(off_keys + sizeof(int32_t) * (size_t)np, 256);
     const size_t off_tb = align_up(off_lists + sizeof(int32_t) * NCLASS * (size_t)np, 256);
     const size_t tb_size = align_up(16 * (size_t)bt->t_nwords + 2 * PADB, 256);
     const size_t off_qb = off_tb + tb_size;
@@ -939,7 +1316,9 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     const bool timed = ctx->timing != 0;
     ctx->timed_last = timed ? 1 : 0;
     if (timed) hipEventRecord(ctx->ev[0], s);
-    hipLaunchKernelGGL(ga_zero_i32, dim3(1), dim3(64), 0, s, counters, (int64_t)CNT_WORDS);
+    // counters and the bucket histogram are contiguous: one fill clears both
+    hipLaunchKernelGGL(ga_zero_i32, dim3((unsigned)((off_cursor / 4 + TB - 1) / TB)), dim3(TB), 0, s,
+                       counters, (int64_t)(off_cursor / 4));
     {
         const int64_t nthr = bt->t_nwords > 2 * PADB / 4 ? bt->t_nwords : 2 * PADB / 4;
         hipLaunchKernelGGL(ga_unpack, dim3((unsigned)((nthr + TB - 1) / TB)), dim3(TB), 0, s, bt->t_words_dev,
@@ -961,10 +1340,15 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     pa.max_len = bt->max_len;
     pa.w = w;
     pa.counters = counters;
+    pa.hist = (int32_t *)(ws + off_hist);
+    pa.cursor = (int32_t *)(ws + off_cursor);
+    pa.keys = (int32_t *)(ws + off_keys);
     pa.lists = lists;
     pa.err = ctx->d_err;
     pa.out = out_dev;
-    hipLaunchKernelGGL(ga_plan, dim3((unsigned)((np + TB - 1) / TB)), dim3(TB), 0, s, pa);
+    hipLaunchKernelGGL(ga_plan_classify, dim3((unsigned)((np + TB - 1) / TB)), dim3(TB), 0, s, pa);
+    hipLaunchKernelGGL(ga_plan_scan, dim3(1), dim3(1024), 0, s, pa);
+    hipLaunchKernelGGL(ga_plan_scatter, dim3((unsigned)((np + TB - 1) / TB)), dim3(TB), 0, s, pa);
     if (timed) hipEventRecord(ctx->ev[1], s);
 
     DpArgs da;
@@ -993,16 +1377,20 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         da.lut_lo = A | (B << 8) | (B << 16) | (B << 24);
         da.lut_hi = N | (N << 8) | (N << 16) | (N << 24);
     }
-    const int64_t want = (int64_t)ctx->num_cu * 8;
-    const int grid = (int)(np < want ? np : want);
     for (int c = 0; c < NCLASS; ++c) {
+        const int64_t want = (int64_t)ctx->num_cu * ctx->blocks_per_cu[c];
+        const int grid = (int)(np < want ? np : want);
         da.cls = c;
         da.list = lists + (size_t)c * np;
         switch (c) {
-        case 0: launch_dp<8>(da, grid, s); break;
-        case 1: launch_dp<16>(da, grid, s); break;
-        case 2: launch_dp<24>(da, grid, s); break;
-        default: launch_dp<32>(da, grid, s); break;
+        case 0: launch_dp<8, 1>(da, grid, s); break;
+        case 1: launch_dp<16, 1>(da, grid, s); break;
+        case 2: launch_dp<24, 1>(da, grid, s); break;
+        case 3: launch_dp<32, 1>(da, grid, s); break;
+        case 4: launch_dp<24, 2>(da, grid, s); break;
+        case 5: launch_dp<32, 2>(da, grid, s); break;
+        case 6: launch_dp<32, 3>(da, grid, s); break;
+        default: launch_dp<32, 4>(da, grid, s); break;
         }
         if (timed) hipEventRecord(ctx->ev[2 + c], s);
     }

@@ -62,3 +62,13 @@ def test_host_validation_without_gpu():
     assert lib.ga_context_destroy(None) == ga.GA_EINVAL
     assert lib.ga_context_check(None, None) == ga.GA_EINVAL
     assert lib.ga_pack(None, None, None, None, 1, 1, None, None, None, None) == ga.GA_EINVAL
+
+
+def test_one_hip_runtime_in_process():
+    """libga.so binds to the HIP runtime torch already loaded (they share a
+    soname); a second runtime in the process would hide the GPU from torch."""
+    import paper_2403_06478_amd as ga
+    ga.load_library()
+    with open("/proc/self/maps") as f:
+        paths = {line.split()[-1] for line in f if "libamdhip64" in line}
+    assert len(paths) == 1, paths
