@@ -1,12 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the MI355X guided extension aligner.
 
-Workload: the ONT-like batch -- 100,000 seeded synthetic pairs, target length
-clip(round(LogNormal(ln 2000, 0.8)), 1, 20000), query = target with 10%
-errors (subst:ins:del 1:1:1), 0.1% N bases scored -1, scoring a=2 b=4 q=4 e=2
-q2=24 e2=1, band w=751, z-drop Z=400. The real long-read datasets the paper
-measures on (GIAB reads after Minimap2 seeding) are not available; these
-pairs stand in for them.
+Default workload (--workload ont): the ONT-like batch -- 100,000 seeded
+synthetic pairs, target length clip(round(LogNormal(ln 2000, 0.8)), 1, 20000),
+query = target with 10% errors (subst:ins:del 1:1:1), 0.1% N bases scored -1,
+scoring a=2 b=4 q=4 e=2 q2=24 e2=1, band w=751, z-drop Z=400. The real
+long-read datasets the paper measures on (GIAB reads after Minimap2 seeding)
+are not available; these pairs stand in for them. --workload longread (20k
+HiFi-like pairs, w=2000) and --workload mixed (1M heavy-tailed pairs) measure
+the other two stand-in workloads.
 
 One step = one ga_align_batch call over the whole batch: base unpacking,
 pair planning and the anti-diagonal sweep with z-drop for every pair. Inputs
@@ -29,6 +31,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (seqgen workload id, description)
+    "ont": (2, "ONT-like batch: 100k pairs, target LogNormal(median 2 kb, sigma 0.8) capped at 20 kb, "
+               "10% errors 1:1:1, 0.1% N scored -1, a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, seed 0"),
+    "longread": (4, "HiFi-like long reads: 20k pairs, target U{10000..25000}, 1% errors 1:1:1 plus 1-3 "
+                    "indels of U{50..500} bp, a=2 b=4 q=4 e=2 q2=24 e2=1, w=2000, Z=5000, seed 0"),
+    "mixed": (3, "heavy-tailed mix: 1M pairs, target min(50000, 50 U^(-1/1.5)), 8% errors 1:1:1, 20% of "
+                 "queries with a U{2000..5000} random insert, a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, "
+                 "seed 0"),
+}
 
 OPS_PER_CELL = 16           # int32 VALU lane-ops per cell (the roofline convention)
 PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # int32 lane-ops/s: CUs x SIMDs x lanes x clock
@@ -79,7 +92,7 @@ def cpu_baseline(batch, n_sample: int):
     dt = time.perf_counter() - t0
     return {"value": round(float(cells.sum()) / dt / 1e9, 4), "unit": "GCUPS", "cores": cores,
             "kind": "oracle",
-            "sample": f"first {sub.n_pairs} pairs of the 100k-pair ONT-like draw "
+            "sample": f"first {sub.n_pairs} pairs of the benchmark batch "
                       f"({int(cells.sum())} cells, {dt:.1f} s)"}
 
 
@@ -88,6 +101,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ont",
+                    help="ont (the headline batch, default), longread or mixed")
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs (profiling runs only)")
     ap.add_argument("--cpu-sample", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -110,8 +125,9 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
-    log("generating the ONT-like workload (100k pairs, seed 0)")
-    batch = seqgen.make_config(2, n_pairs=args.pairs)
+    wid, wdesc = WORKLOADS[args.workload]
+    log(f"generating workload '{args.workload}'")
+    batch = seqgen.make_config(wid, n_pairs=args.pairs)
     ctx = ga.Context(0)
     packed = ga.pack_batch(ctx, batch)
     out = torch.empty((batch.n_pairs, 7), dtype=torch.int32, device="cuda")
@@ -193,9 +209,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "ONT-like batch: 100k pairs, target LogNormal(median 2 kb, sigma 0.8) "
-                               "capped at 20 kb, 10% errors 1:1:1, 0.1% N scored -1, "
-                               "a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, seed 0",
+        "config": {"workload": wdesc,
                    "pairs": batch.n_pairs, "w": batch.w, "Z": batch.zdrop,
                    "cells": total_cells, "zdropped": int(res[:, 6].sum())},
         "pairs_per_s": round(pairs_per_s, 1),

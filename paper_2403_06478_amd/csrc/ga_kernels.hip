@@ -44,6 +44,9 @@ namespace {
 
 constexpr int NEG = -(1 << 30);                  // -inf sentinel; range guard keeps it apart
 constexpr int NEG_MAX = -(1 << 30) - (1 << 29);  // below every reachable value
+// Every finite score in the frame lies above LIVE_MIN (the range guard keeps
+// them within +-2^29); -inf values, even after their drift, lie below it.
+constexpr int LIVE_MIN = -(1 << 29) - (1 << 27);
 constexpr int PADB = 64;                         // guard bytes around the unpacked streams
 constexpr int WAVE = 64;
 
@@ -140,11 +143,11 @@ __device__ __forceinline__ uint32_t window4(const uint32_t *W, int o) {
 
 template <int K>
 struct PairState {
-    // A, E and X are register vectors so the wall slot can be indexed at its
-    // wave-uniform position (s_set_gpr_idx) without leaving registers.
+    // Register vectors, so a slot at a wave-uniform position (the band wall,
+    // a cell leaving the rectangle) can be indexed (s_set_gpr_idx) without
+    // leaving registers.
     typedef int VecK __attribute__((ext_vector_type(K)));
-    VecK A, E, X;
-    int F[K], Y[K];
+    VecK A, E, X, F, Y;
     uint32_t S4[K];  // s' of the slot's next 4 cells, one signed byte each
 };
 
@@ -221,9 +224,34 @@ template <int K>
 __device__ __forceinline__ void clamp_wall(PairState<K> &st, uint64_t wall_lanes, int wall_pos) {
     const bool wl = __builtin_amdgcn_inverse_ballot_w64(wall_lanes);
     const int wp = __builtin_amdgcn_readfirstlane(wall_pos);
-    st.A[wp] = wl ? NEG : st.A[wp];
-    st.E[wp] = wl ? NEG : st.E[wp];
-    st.X[wp] = wl ? NEG : st.X[wp];
+    if (wl) {  // one lane: indexed register writes under its exec mask
+        st.A[wp] = NEG;
+        st.E[wp] = NEG;
+        st.X[wp] = NEG;
+    }
+}
+
+// A cell that has just left the rectangle (the slot at array position p of
+// the class just updated): it feeds only cells outside the rectangle, so it
+// is forced to -inf with the values its successors read -- A, E, X when it
+// is past the target end (i = n: read from above), A, F, Y when it is past
+// the query end (j = m: read from the left). Its successors then stay -inf,
+// and the lane maxima need no mask for them.
+template <int K, bool PAST_T>
+__device__ __forceinline__ void clamp_cell(PairState<K> &st, int p) {
+    const int pl = __builtin_amdgcn_readfirstlane(p);
+    const bool hit = __builtin_amdgcn_inverse_ballot_w64(1ull << (pl / K));
+    const int sl = pl % K;
+    if (hit) {  // one lane: indexed register writes under its exec mask
+        st.A[sl] = NEG;
+        if (PAST_T) {
+            st.E[sl] = NEG;
+            st.X[sl] = NEG;
+        } else {
+            st.F[sl] = NEG;
+            st.Y[sl] = NEG;
+        }
+    }
 }
 
 // Geometry of one pair (all wave-uniform).
@@ -235,6 +263,7 @@ struct Geo {
     int r_last;    // last non-empty anti-diagonal
     int fast_lo, fast_hi;  // anti-diagonals on which every held slot is interior
     bool fast_ok;
+    int a1;        // highest band diagonal
 };
 
 struct Track {
@@ -332,54 +361,62 @@ __device__ __forceinline__ void park_class(const PairState<K> &st, PairLds<K, NW
 // interior on this anti-diagonal). NEG_MAX when the wave holds none.
 template <int K, int C, int NW>
 __device__ __forceinline__ int lane_max(const PairState<K> &st, const Geo &g, int vlo, int vhi, bool masked) {
-    int lm = NEG_MAX;
+    constexpr int H = K / 2;  // class slots C, C+2, ...
+    int v[H];
     if (masked) {
         // this wave's slots inside [vlo, vhi]: a lane range per slot
         // (one wave: [vlo, vhi] lies inside the held band, so no clipping)
         const int u = NW == 1 ? vlo - g.a0w : max(vlo - g.a0w, 0);
-        const int v = NW == 1 ? vhi - g.a0w : min(vhi - g.a0w, WAVE * K - 1);
-        if (NW == 1 || u <= v) {
-            const int qu = u / K, ru = u % K, qv = v / K, rv = v % K;
+        const int vv = NW == 1 ? vhi - g.a0w : min(vhi - g.a0w, WAVE * K - 1);
+        if (NW == 1 || u <= vv) {
+            const int qu = u / K, ru = u % K, qv = vv / K, rv = vv % K;
             const uint64_t lo0 = lanes_from(qu), lo1 = lanes_from(qu + 1);
             const uint64_t hi0 = lanes_upto(qv), hi1 = lanes_upto(qv - 1);
             const int negmax = NEG_MAX;
 #pragma unroll
-            for (int s = C; s < K; s += 2) {
-                const uint64_t msk = (ru > s ? lo1 : lo0) & (rv >= s ? hi0 : hi1);
-                lm = max(lm, select_by_lanes(msk, st.A[s], negmax));
+            for (int t = 0; t < H; ++t) {
+                const int sl = C + 2 * t;
+                const uint64_t msk = (ru > sl ? lo1 : lo0) & (rv >= sl ? hi0 : hi1);
+                v[t] = select_by_lanes(msk, st.A[sl], negmax);
             }
+        } else {
+#pragma unroll
+            for (int t = 0; t < H; ++t) v[t] = NEG_MAX;
         }
     } else {
 #pragma unroll
-        for (int s = C; s < K; s += 2) lm = max(lm, st.A[s]);
+        for (int t = 0; t < H; ++t) v[t] = st.A[C + 2 * t];
+    }
+    // balanced v_max3 tree: depth 2-3 instead of a chain of H/2
+    int w3[(H + 2) / 3];
+#pragma unroll
+    for (int t = 0; t < (H + 2) / 3; ++t) {
+        const int a = v[3 * t];
+        const int b = 3 * t + 1 < H ? v[3 * t + 1] : a;
+        const int c = 3 * t + 2 < H ? v[3 * t + 2] : a;
+        w3[t] = max(max(a, b), c);
+    }
+    int lm = w3[0];
+#pragma unroll
+    for (int t = 1; t < (H + 2) / 3; t += 2) {
+        const int b = w3[t];
+        const int c = t + 1 < (H + 2) / 3 ? w3[t + 1] : b;
+        lm = max(max(lm, b), c);
     }
     return lm;
 }
 
-// One wave per pair, after the class-C update of anti-diagonal r: local
-// maximum (Eq. 6), global maximum (Eq. 7) and the z-drop test (Eq. 5).
-// Returns true when done.
+// One wave per pair: the decisions for anti-diagonal r (class C) from its
+// lane maxima lm and wave maximum MA: local maximum (Eq. 6), global maximum
+// (Eq. 7) and the z-drop test (Eq. 5). They run one step late, after the
+// update of anti-diagonal r+1, which leaves class C untouched. Returns 0 to
+// go on, 1 when the sweep ends at its last anti-diagonal, 2 on a z-drop.
 template <int K, int C>
-__device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &P, const Geo &g,
-                                          Track &tr, int r, int lane, bool masked, PairLds<K, 1> &S) {
-    int vlo = 0, vhi = 0;
-    if (masked) {
-        diag_window(g, r, vlo, vhi);
-        if (vlo > vhi) return r >= g.r_last;  // no interior cell: nothing to test
-    }
-    const int lm = lane_max<K, C, 1>(st, g, vlo, vhi, masked);
-    const bool last = r >= g.r_last;
-    if (!last) {
-        // the wave reduction only matters if some lane is above G (a new
-        // maximum) or every lane is more than Z below it (a z-drop
-        // candidate); two compares settle that for most anti-diagonals
-        const int gF = tr.G - P.q1 + P.e1 * r;  // G in this anti-diagonal's frame
-        const bool up = __ballot(lm > gF) != 0;
-        const bool low = P.Z >= 0 && __ballot(lm >= gF - P.Z) == 0;
-        if (__builtin_expect(!up && !low, 1)) return false;
-    }
-    const int MA = wave_max(lm);
+__device__ __forceinline__ int decide(const PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
+                                       int r, int lane, int lm, int MA, int vlo, int vhi, bool masked,
+                                       PairLds<K, 1> &S) {
     const int M = MA + P.q1 - P.e1 * r;  // back to the true score
+    const bool last = r >= g.r_last;
     if (M > tr.G) {
         park_class<K, C, 1>(st, S, lane);
         tr.G = M;
@@ -391,12 +428,15 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
         tr.g_set = true;
         if (last) {
             if (!masked) diag_window(g, r, vlo, vhi);
-            locate<K, C>(st, g, lm, MA, r, vlo, vhi, tr.endI, tr.endJ);
+            int mi, mj;
+            locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
             tr.endS = M;
+            tr.endI = mi;
+            tr.endJ = mj;
         }
-        return last;
+        return last ? 1 : 0;
     }
-    if ((P.Z >= 0 && tr.G - M > P.Z) || last) {
+    if (__builtin_expect((P.Z >= 0 && tr.G - M > P.Z) || last, 0)) {
         if (!masked) diag_window(g, r, vlo, vhi);
         int mi, mj;
         locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
@@ -405,20 +445,20 @@ __device__ __forceinline__ bool post_step(const PairState<K> &st, const DpArgs &
         tr.endJ = mj;
         if (P.Z >= 0 && tr.G - M > P.Z) {
             if (tr.g_open) {
-                park_cell<K, 1>(tr, g, S, lane, tr.gi, tr.gj);
+                int gi, gj;
+                park_cell<K, 1>(tr, g, S, lane, gi, gj);
+                tr.gi = gi;
+                tr.gj = gj;
                 tr.g_open = false;
             }
             if (mi > tr.gi && mj > tr.gj) {
                 int dd = (mi - tr.gi) - (mj - tr.gj);
                 dd = dd < 0 ? -dd : dd;
-                if (tr.G - M > P.Z + P.e2 * dd) {
-                    tr.zd = 1;
-                    return true;
-                }
+                if (tr.G - M > P.Z + P.e2 * dd) return 2;
             }
         }
     }
-    return last;
+    return last ? 1 : 0;
 }
 
 // Several waves per pair, after the class-C update of anti-diagonal r. One
@@ -541,6 +581,83 @@ __device__ __forceinline__ void read_edges(const PairLds<K, NW> &S, int r, int w
     }
 }
 
+// Frame value (A = H - q, stored + e*r) of the boundary cells (-1, r+1) and
+// (r+1, -1) of anti-diagonal r: H = -gamma(r+2).
+__device__ __forceinline__ int ring_a(const DpArgs &P, int r) {
+    const int l = r + 2;
+    const int gap = min(P.q1 + l * P.e1, P.oe2 + (l - 1) * P.e2);
+    return -gap - P.q1 + P.e1 * r;
+}
+
+// One wave per pair, 8 anti-diagonals r0 .. r0+7. Step T finishes
+// anti-diagonal r-1 (its clamps, lane maxima and wave reduction) in the
+// same straight-line code as the update of anti-diagonal r, so the serial
+// reduction hides among the independent cell updates; the decisions for r-1
+// follow. The last anti-diagonal's decisions therefore come one step after
+// it; the extra anti-diagonal computed meanwhile is never looked at.
+//
+// The lane maxima are unmasked: the wall and the cells leaving the
+// rectangle are clamped to -inf, cells before row/column -1 never leave
+// -inf, and the only other finite cells outside the rectangle are the two
+// boundary cells (-1, r+1), (r+1, -1) while they are in the band. When the
+// wave maximum equals their value the anti-diagonal is redone with masks.
+template <int K>
+__device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
+                                           int r0, int lane, uint64_t wall_lanes, int wall_pos,
+                                           PairLds<K, 1> &S) {
+#define GA_STEP1(T)                                                                        \
+    {                                                                                      \
+        constexpr int C = (T) & 1;                                                         \
+        constexpr int CP = C ^ 1;                                                          \
+        constexpr int KC = (T) >> 1;                                                       \
+        const int r = r0 + (T);                                                            \
+        if (r >= 0) {                                                                      \
+            const int rp = r - 1;                                                          \
+            if (r >= 1) {                                                                  \
+                if (wall_lanes != 0 && (wall_pos & 1) == CP)                               \
+                    clamp_wall<K>(st, wall_lanes, wall_pos);                               \
+                const int di = 2 * g.n - rp;  /* i = n on anti-diagonal rp */              \
+                if (di >= g.a0 && di <= g.a1) clamp_cell<K, true>(st, di - g.a0);          \
+                const int dj = rp - 2 * g.m;  /* j = m */                                  \
+                if (dj >= g.a0 && dj <= g.a1) clamp_cell<K, false>(st, dj - g.a0);         \
+            }                                                                              \
+            int lm = lane_max<K, CP, 1>(st, g, 0, 0, false);                               \
+            int MA = wave_max(lm);                                                         \
+            dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                       \
+            if (r >= 1) {                                                                  \
+                int vlo = 0, vhi = 0;                                                      \
+                bool mp = false;                                                           \
+                const bool ring = rp + 2 <= g.a1 || -rp - 2 >= g.a0;                       \
+                if (__builtin_expect(ring && MA == ring_a(P, rp), 0)) {                    \
+                    /* a boundary cell may hold the maximum: redo it masked */             \
+                    mp = true;                                                             \
+                    diag_window(g, rp, vlo, vhi);                                          \
+                    lm = lane_max<K, CP, 1>(st, g, vlo, vhi, true);                        \
+                    MA = wave_max(lm);                                                     \
+                }                                                                          \
+                if (MA > LIVE_MIN) {  /* the anti-diagonal has an interior cell */         \
+                    const int rc = decide<K, CP>(st, P, g, tr, rp, lane, lm, MA, vlo, vhi, mp, S); \
+                    if (rc) {                                                              \
+                        tr.zd = rc >> 1;                                                   \
+                        return true;                                                       \
+                    }                                                                      \
+                }                                                                          \
+            }                                                                              \
+        }                                                                                  \
+    }
+    GA_STEP1(0)
+    GA_STEP1(1)
+    GA_STEP1(2)
+    GA_STEP1(3)
+    GA_STEP1(4)
+    GA_STEP1(5)
+    GA_STEP1(6)
+    GA_STEP1(7)
+#undef GA_STEP1
+    return false;
+}
+
+// Several waves per pair, 8 anti-diagonals r0 .. r0+7, in order.
 template <int K, int NW>
 __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
                                           Track &tr, int r0, int lane, int wv, uint64_t wall_lanes,
@@ -555,13 +672,8 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
             read_edges<C, K, NW>(S, r, wv, f0, f1, f2);                               \
             dp_step<K, C, KC>(st, P, f0, f1, f2);                                     \
             if (wall_lanes != 0 && (wall_pos & 1) == C) clamp_wall<K>(st, wall_lanes, wall_pos); \
-            if constexpr (NW > 1) publish_edges<K, C, NW>(st, S, r, lane, wv);        \
-            if constexpr (NW == 1) {                                                  \
-                if (post_step<K, C>(st, P, g, tr, r, lane, masked, S)) return true;   \
-            } else {                                                                  \
-                if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, masked, S, p))  \
-                    return true;                                                      \
-            }                                                                         \
+            publish_edges<K, C, NW>(st, S, r, lane, wv);                              \
+            if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, masked, S, p)) return true; \
         }                                                                             \
     }
     GA_STEP(0)
@@ -658,6 +770,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     g.fast_ok = (g.a0 == g.dlo) && (a1 == g.dhi) && (g.dhi > g.dlo);
     g.fast_lo = max(-g.dlo, g.dhi);
     g.fast_hi = min(2 * m - 2 + g.dlo, 2 * n - 2 - g.dhi);
+    g.a1 = a1;
     // the right wall: array position D, in this wave or not
     const int Dw = D - wv * (WAVE * K);
     const bool has_wall = Dw >= 0 && Dw < WAVE * K;
@@ -715,12 +828,21 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         build_scores<K>(st, wd, P);
         load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, d0);  // next block, in flight
         const bool fast = g.fast_ok && r0 >= g.fast_lo && r0 + 7 <= g.fast_hi;
-        const bool done = run_block<K, NW>(st, P, g, tr, r0, lane, wv, wall_lanes, wall_pos, !fast, S, p);
+        bool done;
+        if constexpr (NW == 1)
+            done = run_block1<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, S);
+        else
+            done = run_block<K, NW>(st, P, g, tr, r0, lane, wv, wall_lanes, wall_pos, !fast, S, p);
         if (done) break;
         r0 += 8;
     }
     if constexpr (NW == 1) {
-        if (tr.g_open) park_cell<K, 1>(tr, g, S, lane, tr.gi, tr.gj);
+        if (tr.g_open) {
+            int gi, gj;
+            park_cell<K, 1>(tr, g, S, lane, gi, gj);
+            tr.gi = gi;
+            tr.gj = gj;
+        }
         if (lane < 7) {
             const int v[7] = {tr.G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
             int val = v[0];

@@ -280,3 +280,29 @@ def test_valu_calibration_plausible():
     v = context().calibrate_valu() / 1e12
     _say(f"measured int32 VALU peak {v:.2f} T lane-ops/s")
     assert 0.25 * 39.32 < v < 1.15 * 39.32
+
+
+def test_boundary_cells_never_counted():
+    """Near the origin the boundary cells (-1, r+1) and (r+1, -1) can score
+    above every cell of their anti-diagonal (heavy mismatch penalty, cheap
+    long gaps); they must never become the anti-diagonal maximum. All-mismatch
+    and unrelated pairs over several bands, scorings and thresholds."""
+    rng = np.random.default_rng(606)
+    T, Q = [], []
+    for k in range(60):
+        n, m = int(rng.integers(2, 300)), int(rng.integers(2, 300))
+        if k % 3 == 0:
+            t, q = b"A" * n, b"C" * m
+        else:
+            t = bytes(rng.choice(list(b"ACGT"), n))
+            q = bytes(rng.choice(list(b"ACGT"), m))
+        T.append(t)
+        Q.append(q)
+    for sc in (dict(a=1, b=9, q=1, e=1, q2=6, e2=0, ambig=3),
+               dict(a=2, b=4, q=4, e=2, q2=24, e2=1, ambig=1),
+               dict(a=1, b=6, q=0, e=1, q2=2, e2=0, ambig=6)):
+        for w in (-1, 3, 40, 700):
+            for Z in (-1, 0, 25):
+                b = seqgen.from_lists(T, Q, sc, w, Z)
+                want, _ = oracle_align(b)
+                assert_same(gpu_align(b), want, b, f"boundary sc={sc} w={w} Z={Z}")
