@@ -261,8 +261,6 @@ struct Geo {
     int a0w;       // the first diagonal of this wave's slots (a0 for wave 0)
     int dlo, dhi;  // diagonals with interior cells
     int r_last;    // last non-empty anti-diagonal
-    int fast_lo, fast_hi;  // anti-diagonals on which every held slot is interior
-    bool fast_ok;
     int a1;        // highest band diagonal
 };
 
@@ -289,6 +287,7 @@ struct PairLds {
     int park[K * WAVE];  // park[s * 64 + lane] = A of slot s
     int edge[2][NW][3];
     int ma[2][NW];
+    int ma2[NW];         // wave maxima of an anti-diagonal redone with masks
     int idx;             // pair index handed to every wave
 };
 
@@ -302,6 +301,14 @@ __device__ __forceinline__ void diag_window(const Geo &g, int r, int &vlo, int &
     vhi = min(g.dhi, min(r, 2 * g.n - 2 - r));
     vlo += (vlo - r) & 1;
     vhi -= (vhi - r) & 1;
+}
+
+// Frame value (A = H - q, stored + e*r) of the boundary cells (-1, r+1) and
+// (r+1, -1) of anti-diagonal r: H = -gamma(r+2).
+__device__ __forceinline__ int ring_a(const DpArgs &P, int r) {
+    const int l = r + 2;
+    const int gap = min(P.q1 + l * P.e1, P.oe2 + (l - 1) * P.e2);
+    return -gap - P.q1 + P.e1 * r;
 }
 
 // Smallest-i cell attaining the frame value MA among the class-C slots of
@@ -472,16 +479,12 @@ __device__ __forceinline__ int decide(const PairState<K> &st, const DpArgs &P, c
 // computed is never looked at). Returns true when done.
 template <int K, int C, int NW>
 __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArgs &P, const Geo &g,
-                                             Track &tr, int r, int lane, int wv, bool masked,
-                                             PairLds<K, NW> &S, int p) {
-    int vlo = 0, vhi = 0;
-    bool any = true;  // the anti-diagonal has interior cells
-    if (masked) {
-        diag_window(g, r, vlo, vhi);
-        any = vlo <= vhi;
-    }
-    const int lm = any ? lane_max<K, C, NW>(st, g, vlo, vhi, masked) : NEG_MAX;
-    const int MAw = wave_max(lm);
+                                             Track &tr, int r, int lane, int wv, PairLds<K, NW> &S,
+                                             int p) {
+    // unmasked lane maxima: outside the rectangle only the two boundary
+    // cells can be finite (the cells past either end are clamped)
+    int lm = lane_max<K, C, NW>(st, g, 0, 0, false);
+    int MAw = wave_max(lm);
     const int b = r & 1;
     if (lane == 0) S.ma[b][wv] = tr.stop ? STOP : MAw;
     __syncthreads();
@@ -500,7 +503,29 @@ __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArg
     }
     if (stop) return true;
     const bool last = r >= g.r_last;
-    if (!any) return last;
+    int vlo = 0, vhi = 0;
+    bool masked = false;
+    const bool ring = r + 2 <= g.a1 || -r - 2 >= g.a0;
+    if (__builtin_expect(ring && MA == ring_a(P, r), 0)) {
+        // a boundary cell may hold the maximum: redo the anti-diagonal masked
+        masked = true;
+        diag_window(g, r, vlo, vhi);
+        lm = vlo <= vhi ? lane_max<K, C, NW>(st, g, vlo, vhi, true) : NEG_MAX;
+        MAw = wave_max(lm);
+        if (lane == 0) S.ma2[wv] = MAw;
+        __syncthreads();
+        MA = __builtin_amdgcn_readfirstlane(S.ma2[0]);
+        vstar = 0;
+#pragma unroll
+        for (int k = 1; k < NW; ++k) {
+            const int x = __builtin_amdgcn_readfirstlane(S.ma2[k]);
+            if (x > MA) {
+                MA = x;
+                vstar = k;
+            }
+        }
+    }
+    if (MA <= LIVE_MIN) return last;  // no interior cell on this anti-diagonal
     const int M = MA + P.q1 - P.e1 * r;  // back to the true score
     const bool up = M > tr.G;
     if (up) {
@@ -581,13 +606,6 @@ __device__ __forceinline__ void read_edges(const PairLds<K, NW> &S, int r, int w
     }
 }
 
-// Frame value (A = H - q, stored + e*r) of the boundary cells (-1, r+1) and
-// (r+1, -1) of anti-diagonal r: H = -gamma(r+2).
-__device__ __forceinline__ int ring_a(const DpArgs &P, int r) {
-    const int l = r + 2;
-    const int gap = min(P.q1 + l * P.e1, P.oe2 + (l - 1) * P.e2);
-    return -gap - P.q1 + P.e1 * r;
-}
 
 // One wave per pair, 8 anti-diagonals r0 .. r0+7. Step T finishes
 // anti-diagonal r-1 (its clamps, lane maxima and wave reduction) in the
@@ -661,7 +679,7 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
 template <int K, int NW>
 __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
                                           Track &tr, int r0, int lane, int wv, uint64_t wall_lanes,
-                                          int wall_pos, bool masked, PairLds<K, NW> &S, int p) {
+                                          int wall_pos, PairLds<K, NW> &S, int p) {
 #define GA_STEP(T)                                                                    \
     {                                                                                 \
         constexpr int C = (T) & 1;                                                    \
@@ -672,8 +690,16 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
             read_edges<C, K, NW>(S, r, wv, f0, f1, f2);                               \
             dp_step<K, C, KC>(st, P, f0, f1, f2);                                     \
             if (wall_lanes != 0 && (wall_pos & 1) == C) clamp_wall<K>(st, wall_lanes, wall_pos); \
+            {   /* cells leaving the rectangle, in the wave holding them */           \
+                const int pi = 2 * g.n - r - g.a0 - wv * (WAVE * K);                  \
+                if (2 * g.n - r <= g.a1 && pi >= 0 && pi < WAVE * K)                  \
+                    clamp_cell<K, true>(st, pi);                                      \
+                const int pj = r - 2 * g.m - g.a0 - wv * (WAVE * K);                  \
+                if (r - 2 * g.m >= g.a0 && pj >= 0 && pj < WAVE * K)                  \
+                    clamp_cell<K, false>(st, pj);                                     \
+            }                                                                         \
             publish_edges<K, C, NW>(st, S, r, lane, wv);                              \
-            if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, masked, S, p)) return true; \
+            if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, S, p)) return true; \
         }                                                                             \
     }
     GA_STEP(0)
@@ -766,10 +792,6 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         const int dc = min(max(n - m, g.dlo), g.dhi);
         g.r_last = min(2 * n - 2 - dc, 2 * m - 2 + dc);
     }
-    // fast blocks: both band edges are walls and both parities have cells
-    g.fast_ok = (g.a0 == g.dlo) && (a1 == g.dhi) && (g.dhi > g.dlo);
-    g.fast_lo = max(-g.dlo, g.dhi);
-    g.fast_hi = min(2 * m - 2 + g.dlo, 2 * n - 2 - g.dhi);
     g.a1 = a1;
     // the right wall: array position D, in this wave or not
     const int Dw = D - wv * (WAVE * K);
@@ -827,12 +849,11 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     for (;;) {
         build_scores<K>(st, wd, P);
         load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, d0);  // next block, in flight
-        const bool fast = g.fast_ok && r0 >= g.fast_lo && r0 + 7 <= g.fast_hi;
         bool done;
         if constexpr (NW == 1)
             done = run_block1<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, S);
         else
-            done = run_block<K, NW>(st, P, g, tr, r0, lane, wv, wall_lanes, wall_pos, !fast, S, p);
+            done = run_block<K, NW>(st, P, g, tr, r0, lane, wv, wall_lanes, wall_pos, S, p);
         if (done) break;
         r0 += 8;
     }
