@@ -46,7 +46,7 @@ WORKLOADS = {
 OPS_PER_CELL = 16           # int32 VALU lane-ops per cell (the roofline convention)
 PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # int32 lane-ops/s: CUs x SIMDs x lanes x clock
 DOMINANT_KERNEL_SRC = os.path.join(ROOT, "paper_2403_06478_amd", "csrc", "ga_kernels.hip")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "ga_dp_kernel_k24_cfg2_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "ga_dp_kernel_k24_ont100k_pmc.md")
 
 
 def log(msg: str):
