@@ -126,16 +126,21 @@ int ga_context_set_timing(ga_context_t *ctx, int enable);
 
 /* Milliseconds spent by the stages of the last timed ga_align_batch on this
  * context (waits for those events): ms[0] = unpack + planning kernels,
- * ms[1+c] = the alignment kernel of class c, for c < n-1 and c < 8. Class c
- * runs K slots per lane and W waves per pair, holding bands of up to 64*K*W
- * diagonals: (K, W) = (8,1) (16,1) (24,1) (32,1) (24,2) (32,2) (32,3) (32,4).
+ * ms[1+c] = the alignment kernel of class c, for c < n-1 and c < 11. Class
+ * c runs K slots per lane and W waves per pair: (K, W) = (4,1) (8,1) (16,1)
+ * (24,1) (32,1) hold bands of up to 64*K*W diagonals; (8,1) (16,1) with a
+ * sliding window run pairs whose shorter sequence s has 2s + 11 + K <= 64K
+ * whatever the band; (24,2) (32,2) (32,3) (32,4) hold bands of up to 64*K*W
+ * diagonals.
  * GA_EINVAL if timing was off for that call. */
 int ga_context_timing(ga_context_t *ctx, float *ms, int n);
 
-/* Class (0..7, see ga_context_timing) that ga_align_batch uses for a pair
- * of lengths n, m at band w: the first whose kernel holds the band's
- * min(w, n) + min(w, m) + 1 diagonals (all n + m + 1 when w < 0); -1 for an
- * empty pair or a band wider than the kernels hold.
+/* Class (0..10, see ga_context_timing) that ga_align_batch uses for a pair
+ * of lengths n, m at band w: the cheapest whose kernel holds the band's
+ * min(w, n) + min(w, m) + 1 diagonals (all n + m + 1 when w < 0), or, for a
+ * sliding class, the pair's 2 min(n, m) + 11 + K; -1 for an empty pair or
+ * a band wider than the kernels hold. Cheapest means fewest slots per lane
+ * (4, 8, sliding 8, 16, sliding 16, 24, 32), then the multi-wave classes.
  * Host function, for attributing work to the per-class kernels. */
 int ga_pair_class(int32_t n, int32_t m, int32_t w);
 

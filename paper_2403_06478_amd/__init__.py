@@ -33,16 +33,18 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
                "ga_calibrate_valu")
 
-# Alignment kernels by class: (slots per lane K, waves per pair); class c
-# holds bands of up to 64 * K * waves diagonals.
-CLASSES = ((8, 1), (16, 1), (24, 1), (32, 1), (24, 2), (32, 2), (32, 3), (32, 4))
-CLASS_SLOTS = tuple(k for k, _ in CLASSES)
+# Alignment kernels by class: (slots per lane K, waves per pair, sliding
+# window). A fixed class holds bands of up to 64 * K * waves diagonals; a
+# sliding one-wave class runs a short-by-long pair whose band is wider.
+CLASSES = ((4, 1, False), (8, 1, False), (16, 1, False), (24, 1, False), (32, 1, False),
+           (8, 1, True), (16, 1, True), (24, 2, False), (32, 2, False), (32, 3, False), (32, 4, False))
+CLASS_SLOTS = tuple(k for k, _, _ in CLASSES)
 MAX_DIAGONALS = 64 * 32 * 4
 
 
 def class_name(c: int) -> str:
-    k, nw = CLASSES[c]
-    return f"ga_dp_kernel<{k},{nw}>"
+    k, nw, sl = CLASSES[c]
+    return f"ga_dp_kernel<{k},{nw},{'sliding' if sl else 'fixed'}>"
 
 
 class GaError(RuntimeError):
@@ -160,7 +162,7 @@ class Context:
         _check(load_library().ga_context_set_timing(self._h, 1 if enable else 0), "ga_context_set_timing")
 
     def timing(self):
-        """Stage milliseconds of the last timed call: [prep, class 0 .. class 7]."""
+        """Stage milliseconds of the last timed call: [prep, class 0 .. class 10]."""
         n = 1 + len(CLASSES)
         ms = (ctypes.c_float * n)()
         _check(load_library().ga_context_timing(self._h, ms, n), "ga_context_timing")

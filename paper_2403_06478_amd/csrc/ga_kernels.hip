@@ -52,19 +52,52 @@ constexpr int WAVE = 64;
 
 // Slot classes: K slots per lane and NW waves per pair hold the band's
 // D <= 64*K*NW diagonals; a pair goes to the first class that holds it.
-constexpr int NCLASS = 8;
-__host__ __device__ constexpr int class_k(int c) { return c == 0 ? 8 : c == 1 ? 16 : (c == 2 || c == 4) ? 24 : 32; }
-__host__ __device__ constexpr int class_nw(int c) { return c < 4 ? 1 : c < 6 ? 2 : c == 6 ? 3 : 4; }
+constexpr int NCLASS = 11;
+// (K, NW, window) = (4,1,fixed) (8,1,fixed) (16,1,fixed) (24,1,fixed)
+// (32,1,fixed) (8,1,sliding) (16,1,sliding) (24,2,fixed) (32,2,fixed)
+// (32,3,fixed) (32,4,fixed)
+__host__ __device__ constexpr int class_k(int c) {
+    return c == 0 ? 4 : (c == 1 || c == 5) ? 8 : (c == 2 || c == 6) ? 16 : (c == 3 || c == 7) ? 24 : 32;
+}
+__host__ __device__ constexpr int class_nw(int c) { return c < 7 ? 1 : c < 9 ? 2 : c == 9 ? 3 : 4; }
+__host__ __device__ constexpr bool class_slides(int c) { return c == 5 || c == 6; }
 __host__ __device__ constexpr int class_cap(int c) { return WAVE * class_k(c) * class_nw(c); }
 constexpr int MAX_DIAGONALS = WAVE * 32 * 4;
 
-__host__ __device__ inline int class_of(int64_t D) {
-    for (int c = 0; c < NCLASS; ++c)
-        if (D <= class_cap(c)) return c;
+// The class a pair runs in, and whether its one wave slides along the band
+// (*slide = -1 down, +1 up, 0 fixed). A band of D diagonals fits class c when
+// D <= 64*K*NW. When one sequence is short, an anti-diagonal's cells from the
+// boundary cell to the cell just past the short sequence's end span at most
+// 2*min(n,m) + 3 diagonals; a single wave whose window follows them (moved
+// one lane at a time, hence the K of slack) runs such a pair even when the
+// whole band would not fit.
+__host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *slide) {
+    int64_t a0, a1;
+    if (w >= 0) {
+        a0 = -w > -m ? -w : -m;
+        a1 = w < n ? w : n;
+    } else {
+        a0 = -m;
+        a1 = n;
+    }
+    const int64_t D = a1 - a0 + 1;
+    const int64_t span = 2 * (n < m ? n : m) + 11;
+    *slide = 0;
+    // cheapest first: fewer slots per lane, then fewer waves
+    const int order[NCLASS] = {0, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10};
+    for (int k = 0; k < NCLASS; ++k) {
+        const int c = order[k];
+        if (!class_slides(c)) {
+            if (D <= class_cap(c)) return c;
+        } else if (span + class_k(c) <= class_cap(c)) {
+            *slide = n <= m ? -1 : 1;
+            return c;
+        }
+    }
     return -1;
 }
 
-// Device counters (per call): [0..8) class list sizes, [8..16) class heads.
+// Device counters (per call): [0..11) class list sizes, [11..22) class heads.
 // They sit right before the planning histogram in the workspace.
 constexpr int CNT_COUNT = 0;
 constexpr int CNT_HEAD = NCLASS;
@@ -271,7 +304,7 @@ struct Track {
     // where G was taken, kept lazily: the anti-diagonal, the wave holding
     // the cell, the slot class and the frame value; the holding wave parks
     // that class's values in LDS until the cell is needed
-    int g_r, g_wave, g_cls, g_ma;
+    int g_r, g_base, g_cls, g_ma;  // g_base: diagonal of lane 0's slot 0 in the holding wave
     bool g_open;  // G moved since its cell was last resolved
     bool g_set;   // G has moved off the origin
     bool stop;    // (several waves) this wave found the z-drop: tell the others
@@ -340,7 +373,7 @@ __device__ __forceinline__ void park_cell(const Track &tr, const Geo &g, const P
                                           int &gi, int &gj) {
     int vlo, vhi;
     diag_window(g, tr.g_r, vlo, vhi);
-    const int dl = g.a0 + (tr.g_wave * WAVE + lane) * K + tr.g_cls;  // this lane's first class slot
+    const int dl = tr.g_base + lane * K + tr.g_cls;  // this lane's first class slot
     int hit = K;
 #pragma unroll
     for (int t = K / 2 - 1; t >= 0; --t) {
@@ -350,7 +383,7 @@ __device__ __forceinline__ void park_cell(const Track &tr, const Geo &g, const P
     }
     const int L = __builtin_ctzll(__ballot(hit < K));
     const int t = __builtin_amdgcn_readlane(hit, L);
-    const int dm = g.a0 + (tr.g_wave * WAVE + L) * K + tr.g_cls + 2 * t;
+    const int dm = tr.g_base + L * K + tr.g_cls + 2 * t;
     gi = (tr.g_r + dm) >> 1;
     gj = (tr.g_r - dm) >> 1;
 }
@@ -372,10 +405,9 @@ __device__ __forceinline__ int lane_max(const PairState<K> &st, const Geo &g, in
     int v[H];
     if (masked) {
         // this wave's slots inside [vlo, vhi]: a lane range per slot
-        // (one wave: [vlo, vhi] lies inside the held band, so no clipping)
-        const int u = NW == 1 ? vlo - g.a0w : max(vlo - g.a0w, 0);
-        const int vv = NW == 1 ? vhi - g.a0w : min(vhi - g.a0w, WAVE * K - 1);
-        if (NW == 1 || u <= vv) {
+        const int u = max(vlo - g.a0w, 0);
+        const int vv = min(vhi - g.a0w, WAVE * K - 1);
+        if (u <= vv) {
             const int qu = u / K, ru = u % K, qv = vv / K, rv = vv % K;
             const uint64_t lo0 = lanes_from(qu), lo1 = lanes_from(qu + 1);
             const uint64_t hi0 = lanes_upto(qv), hi1 = lanes_upto(qv - 1);
@@ -428,7 +460,7 @@ __device__ __forceinline__ int decide(const PairState<K> &st, const DpArgs &P, c
         park_class<K, C, 1>(st, S, lane);
         tr.G = M;
         tr.g_r = r;
-        tr.g_wave = 0;
+        tr.g_base = g.a0w;
         tr.g_cls = C;
         tr.g_ma = MA;
         tr.g_open = true;
@@ -532,7 +564,7 @@ __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArg
         if (wv == vstar) park_class<K, C, NW>(st, S, lane);
         tr.G = M;
         tr.g_r = r;
-        tr.g_wave = vstar;
+        tr.g_base = g.a0 + vstar * (WAVE * K);
         tr.g_cls = C;
         tr.g_ma = MA;
         tr.g_set = true;
@@ -635,9 +667,11 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
                 if (wall_lanes != 0 && (wall_pos & 1) == CP)                               \
                     clamp_wall<K>(st, wall_lanes, wall_pos);                               \
                 const int di = 2 * g.n - rp;  /* i = n on anti-diagonal rp */              \
-                if (di >= g.a0 && di <= g.a1) clamp_cell<K, true>(st, di - g.a0);          \
+                const int pi = di - g.a0w;                                                 \
+                if (di <= g.a1 && pi >= 0 && pi < WAVE * K) clamp_cell<K, true>(st, pi);   \
                 const int dj = rp - 2 * g.m;  /* j = m */                                  \
-                if (dj >= g.a0 && dj <= g.a1) clamp_cell<K, false>(st, dj - g.a0);         \
+                const int pj = dj - g.a0w;                                                 \
+                if (dj >= g.a0 && pj >= 0 && pj < WAVE * K) clamp_cell<K, false>(st, pj); \
             }                                                                              \
             int lm = lane_max<K, CP, 1>(st, g, 0, 0, false);                               \
             int MA = wave_max(lm);                                                         \
@@ -770,7 +804,53 @@ __device__ __forceinline__ void build_scores(PairState<K> &st, const Windows<K> 
     }
 }
 
-template <int K, int NW>
+// A sliding wave's first diagonal for the block of anti-diagonals r0 ..
+// r0+7 (then anti-diagonal r0-1, finished in that block, too), moved from
+// `base` by whole lanes. Sliding down (n <= m) it keeps the boundary cell
+// (-1, r+1) on diagonal -r-2 in the window, stopping at a0 (base stays a
+// multiple of K above a0, so lane 0's -inf fill becomes the band wall there);
+// below the window every cell is before column -1, hence -inf. Sliding up it
+// keeps the boundary cell (r+1, -1) on diagonal r+2, or the band wall a1+1,
+// in the window; below it every cell is past the query end. The class
+// choice guarantees the other end of the window still covers every cell
+// that can be finite (see class_for).
+template <int K>
+__device__ __forceinline__ int window_base(const Geo &g, int slide, int base, int r0) {
+    if (slide < 0) {
+        while (base - K >= g.a0 && base > -r0 - 9) base -= K;
+    } else if (slide > 0) {
+        const int need = min(g.a1 + 1, r0 + 9);
+        while (base + WAVE * K - 1 < need) base += K;
+    }
+    return base;
+}
+
+// Move the window one lane: down (dir < 0: lane l takes lane l-1's slots,
+// lane 0 starts at -inf) or up (lane l takes lane l+1's, lane 63 at -inf).
+template <int K>
+__device__ __forceinline__ void shift_lanes(PairState<K> &st, int dir) {
+    if (dir < 0) {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            st.A[s] = dpp_from_lower_lane(NEG, st.A[s]);
+            st.E[s] = dpp_from_lower_lane(NEG, st.E[s]);
+            st.X[s] = dpp_from_lower_lane(NEG, st.X[s]);
+            st.F[s] = dpp_from_lower_lane(NEG, st.F[s]);
+            st.Y[s] = dpp_from_lower_lane(NEG, st.Y[s]);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            st.A[s] = dpp_from_upper_lane(NEG, st.A[s]);
+            st.E[s] = dpp_from_upper_lane(NEG, st.E[s]);
+            st.X[s] = dpp_from_upper_lane(NEG, st.X[s]);
+            st.F[s] = dpp_from_upper_lane(NEG, st.F[s]);
+            st.Y[s] = dpp_from_upper_lane(NEG, st.Y[s]);
+        }
+    }
+}
+
+template <int K, int NW, bool SL>
 __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, NW> &S) {
     Geo g;
     g.n = P.t_len[p];
@@ -793,11 +873,20 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         g.r_last = min(2 * n - 2 - dc, 2 * m - 2 + dc);
     }
     g.a1 = a1;
-    // the right wall: array position D, in this wave or not
-    const int Dw = D - wv * (WAVE * K);
-    const bool has_wall = Dw >= 0 && Dw < WAVE * K;
-    const int wall_pos = has_wall ? Dw % K : 0;
-    const uint64_t wall_lanes = has_wall ? (1ull << (Dw / K)) : 0ull;
+    // one wave on a band wider than it holds: the window slides (class_for)
+    const int slide = (SL && D > WAVE * K) ? (n <= m ? -1 : 1) : 0;
+    int r0 = (g.a0 & 1) ? -1 : -2;  // blocks of 8 anti-diagonals start on the class of slot 0
+    if (slide < 0) g.a0w = g.a0 + K * max(0, (-r0 - 9 - g.a0) / K);
+    // the right wall: the slot of diagonal a1+1, if this wave holds it
+    int wall_pos = 0;
+    uint64_t wall_lanes = 0;
+    auto place_wall = [&]() {
+        const int Dw = a1 + 1 - g.a0w;
+        const bool has_wall = Dw >= 0 && Dw < WAVE * K;
+        wall_pos = has_wall ? Dw % K : 0;
+        wall_lanes = has_wall ? (1ull << (Dw / K)) : 0ull;
+    };
+    place_wall();
 
     const int d0 = g.a0w + lane * K;
     PairState<K> st;
@@ -833,8 +922,6 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
 
     const uint8_t *tbase = P.tb + 16 * P.t_off[p];
     const uint8_t *qbase = P.qb + 16 * P.q_off[p];
-    // blocks of 8 anti-diagonals, each starting on the class of slot 0
-    int r0 = (g.a0 & 1) ? -1 : -2;
     if constexpr (NW > 1) {
         // the edges of anti-diagonal -1 for the first step (anti-diagonal 0,
         // class 2 + r0, i.e. 0 when r0 = -2 and 1 when r0 = -1)
@@ -846,9 +933,19 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     }
     Windows<K> wd;
     load_windows<K>(wd, tbase, qbase, n, m, r0, d0);
+    int base_next = g.a0w;
     for (;;) {
+        if (slide != 0 && base_next != g.a0w) {
+            // move the window to this block's base, one lane at a time
+            const int dir = base_next < g.a0w ? -1 : 1;
+            const int lanes = (base_next - g.a0w) * dir / K;  // whole lanes by construction
+            for (int k = 0; k < lanes && k < WAVE; ++k) shift_lanes<K>(st, dir);
+            g.a0w = base_next;
+            place_wall();
+        }
         build_scores<K>(st, wd, P);
-        load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, d0);  // next block, in flight
+        base_next = slide != 0 ? window_base<K>(g, slide, g.a0w, r0 + 8) : g.a0w;
+        load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, base_next + lane * K);  // next block, in flight
         bool done;
         if constexpr (NW == 1)
             done = run_block1<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, S);
@@ -875,16 +972,17 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     // (several waves: the wave that ended the sweep has written the result)
 }
 
-// Waves per SIMD each slot count is compiled for (register budget).
-template <int K>
+// Waves per SIMD each kernel is compiled for (register budget; a sliding
+// window needs room for the lane shifts).
+template <int K, bool SL>
 struct Occ {
-    static constexpr int value = K <= 8 ? 4 : (K <= 16 ? 3 : 2);
+    static constexpr int value = K <= 8 ? 4 : (K <= 16 && !SL ? 3 : 2);
 };
 
 // Persistent kernel: each workgroup of NW waves takes pairs of its class from
 // the cost-ordered list through an atomic head until the list is exhausted.
-template <int K, int NW>
-__global__ __launch_bounds__(WAVE * NW, Occ<K>::value) void ga_dp_kernel(DpArgs P) {
+template <int K, int NW, bool SL>
+__global__ __launch_bounds__(WAVE * NW, (Occ<K, SL>::value)) void ga_dp_kernel(DpArgs P) {
     __shared__ PairLds<K, NW> S;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -902,7 +1000,7 @@ __global__ __launch_bounds__(WAVE * NW, Occ<K>::value) void ga_dp_kernel(DpArgs 
         }
         if (idx >= count) break;
         const int p = P.list[idx];
-        align_pair<K, NW>(P, p, lane, wv, S);
+        align_pair<K, NW, SL>(P, p, lane, wv, S);
     }
 }
 
@@ -1018,8 +1116,8 @@ __global__ void ga_plan_classify(PlanArgs A) {
             a0 = -m;
             a1 = n;
         }
-        const int D = a1 - a0 + 1;
-        const int cls = class_of(D);
+        int slide;
+        const int cls = class_for(n, m, A.w, &slide);
         if (cls < 0) {
             atomicOr(A.err, 2);
             A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
@@ -1196,15 +1294,15 @@ struct SetDevice {
     }
 };
 
-template <int K, int NW>
+template <int K, int NW, bool SL>
 void launch_dp(const DpArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((ga_dp_kernel<K, NW>), dim3(grid), dim3(WAVE * NW), 0, s, a);
+    hipLaunchKernelGGL((ga_dp_kernel<K, NW, SL>), dim3(grid), dim3(WAVE * NW), 0, s, a);
 }
 
-template <int K, int NW>
+template <int K, int NW, bool SL>
 int blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ga_dp_kernel<K, NW>, WAVE * NW, 0) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ga_dp_kernel<K, NW, SL>, WAVE * NW, 0) != hipSuccess) {
         (void)hipGetLastError();
         nb = 0;
     }
@@ -1242,14 +1340,17 @@ int ga_context_create(ga_context_t **out, int device) {
     if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         ctx->num_cu = 256;
     // persistent grids: as many workgroups as the registers let reside
-    ctx->blocks_per_cu[0] = blocks_per_cu<8, 1>();
-    ctx->blocks_per_cu[1] = blocks_per_cu<16, 1>();
-    ctx->blocks_per_cu[2] = blocks_per_cu<24, 1>();
-    ctx->blocks_per_cu[3] = blocks_per_cu<32, 1>();
-    ctx->blocks_per_cu[4] = blocks_per_cu<24, 2>();
-    ctx->blocks_per_cu[5] = blocks_per_cu<32, 2>();
-    ctx->blocks_per_cu[6] = blocks_per_cu<32, 3>();
-    ctx->blocks_per_cu[7] = blocks_per_cu<32, 4>();
+    ctx->blocks_per_cu[0] = blocks_per_cu<4, 1, false>();
+    ctx->blocks_per_cu[1] = blocks_per_cu<8, 1, false>();
+    ctx->blocks_per_cu[2] = blocks_per_cu<16, 1, false>();
+    ctx->blocks_per_cu[3] = blocks_per_cu<24, 1, false>();
+    ctx->blocks_per_cu[4] = blocks_per_cu<32, 1, false>();
+    ctx->blocks_per_cu[5] = blocks_per_cu<8, 1, true>();
+    ctx->blocks_per_cu[6] = blocks_per_cu<16, 1, true>();
+    ctx->blocks_per_cu[7] = blocks_per_cu<24, 2, false>();
+    ctx->blocks_per_cu[8] = blocks_per_cu<32, 2, false>();
+    ctx->blocks_per_cu[9] = blocks_per_cu<32, 3, false>();
+    ctx->blocks_per_cu[10] = blocks_per_cu<32, 4, false>();
     if (hipMalloc(&ctx->d_err, sizeof(int32_t)) != hipSuccess) {
         (void)hipGetLastError();
         free(ctx);
@@ -1324,7 +1425,8 @@ int ga_pair_class(int32_t n, int32_t m, int32_t w) {
         a0 = -m;
         a1 = n;
     }
-    return class_of(a1 - a0 + 1);
+    int slide;
+    return class_for(n, m, w, &slide);
 }
 
 int64_t ga_pack_words(const int32_t *len_host, int64_t n) {
@@ -1526,14 +1628,17 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         da.cls = c;
         da.list = lists + (size_t)c * np;
         switch (c) {
-        case 0: launch_dp<8, 1>(da, grid, s); break;
-        case 1: launch_dp<16, 1>(da, grid, s); break;
-        case 2: launch_dp<24, 1>(da, grid, s); break;
-        case 3: launch_dp<32, 1>(da, grid, s); break;
-        case 4: launch_dp<24, 2>(da, grid, s); break;
-        case 5: launch_dp<32, 2>(da, grid, s); break;
-        case 6: launch_dp<32, 3>(da, grid, s); break;
-        default: launch_dp<32, 4>(da, grid, s); break;
+        case 0: launch_dp<4, 1, false>(da, grid, s); break;
+        case 1: launch_dp<8, 1, false>(da, grid, s); break;
+        case 2: launch_dp<16, 1, false>(da, grid, s); break;
+        case 3: launch_dp<24, 1, false>(da, grid, s); break;
+        case 4: launch_dp<32, 1, false>(da, grid, s); break;
+        case 5: launch_dp<8, 1, true>(da, grid, s); break;
+        case 6: launch_dp<16, 1, true>(da, grid, s); break;
+        case 7: launch_dp<24, 2, false>(da, grid, s); break;
+        case 8: launch_dp<32, 2, false>(da, grid, s); break;
+        case 9: launch_dp<32, 3, false>(da, grid, s); break;
+        default: launch_dp<32, 4, false>(da, grid, s); break;
         }
         if (timed) hipEventRecord(ctx->ev[2 + c], s);
     }

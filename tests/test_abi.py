@@ -72,3 +72,34 @@ def test_one_hip_runtime_in_process():
     with open("/proc/self/maps") as f:
         paths = {line.split()[-1] for line in f if "libamdhip64" in line}
     assert len(paths) == 1, paths
+
+
+def test_pair_class_rule():
+    """Host class choice: the cheapest kernel that holds the pair -- a fixed
+    class when the band's diagonals fit, a sliding one-wave class when the
+    shorter sequence's span does, else the multi-wave classes by band."""
+    import numpy as np
+
+    import paper_2403_06478_amd as ga
+    rng = np.random.default_rng(5)
+    order = [0, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10]
+    for _ in range(3000):
+        n, m = (int(x) for x in rng.integers(0, 9000, 2))
+        w = int(rng.choice([-1, 0, 1, 100, 751, 2000, 4095, 5000]))
+        got = ga.ga_pair_class(n, m, w)
+        if n == 0 or m == 0:
+            assert got == -1
+            continue
+        a0, a1 = (max(-w, -m), min(w, n)) if w >= 0 else (-m, n)
+        D = a1 - a0 + 1
+        want = -1
+        for c in order:
+            k, nw, sl = ga.CLASSES[c]
+            cap = 64 * k * nw
+            if (not sl and D <= cap) or (sl and 2 * min(n, m) + 11 + k <= cap):
+                want = c
+                break
+        assert got == want, (n, m, w, got, want)
+        if got >= 0 and not ga.CLASSES[got][2]:
+            k, nw, _ = ga.CLASSES[got]
+            assert D <= 64 * k * nw

@@ -183,7 +183,7 @@ def test_multiwave_bands(w):
                             w=w, zdrop=int(rng.choice([-1, 150, 400])))
     cls = [ga.ga_pair_class(int(n), int(m), w) for n, m in zip(b.t_len, b.q_len)]
     _say(f"multiwave w={w} Z={b.zdrop}: classes {sorted(set(cls))}")
-    assert max(cls) >= 4
+    assert max(cls) >= 5  # a multi-wave class
     want, _ = oracle_align(b)
     assert_same(gpu_align(b), want, b, f"multiwave w={w}")
 
@@ -306,3 +306,46 @@ def test_boundary_cells_never_counted():
                 b = seqgen.from_lists(T, Q, sc, w, Z)
                 want, _ = oracle_align(b)
                 assert_same(gpu_align(b), want, b, f"boundary sc={sc} w={w} Z={Z}")
+
+
+@pytest.mark.parametrize("w", [-1, 300, 751, 2000])
+def test_sliding_window_short_by_long(w):
+    """One short and one long sequence: the band is wider than one wave
+    holds, but a single wave whose window follows the anti-diagonals' cells
+    runs the pair. Short target or short query (the window moves down or
+    up), related and unrelated pairs (z-drops mid-way), N bases, and a short
+    side near the sliding limit of each class."""
+    import paper_2403_06478_amd as ga
+    rng = np.random.default_rng(9000 + max(w, 0))
+    T, Q = [], []
+    def seq(alphabet, k, p=None):
+        return rng.choice(np.frombuffer(alphabet, dtype=np.uint8), k, p=p).tobytes()
+
+    for k in range(36):
+        s = int(rng.choice([3, 40, 150, 240, 470]))
+        # unbanded: keep 2 * max_len + 1 within the 8192 diagonals the host accepts
+        l = int(rng.integers(1500, 4000 if w < 0 else 6000))
+        base = seq(b"ACGT", l)
+        if k % 3 == 0:
+            short = seq(b"ACGTN", s, p=[0.24, 0.24, 0.24, 0.24, 0.04])
+        else:
+            off = int(rng.integers(0, max(1, min(l - s, 60))))
+            short = bytearray(base[off:off + s])
+            for t in range(len(short)):
+                if rng.random() < 0.08:
+                    short[t] = b"ACGT"[int(rng.integers(0, 4))]
+            short = bytes(short)
+        if k % 2 == 0:
+            T.append(short)
+            Q.append(base)
+        else:
+            T.append(base)
+            Q.append(short)
+    for Z in (-1, 60, 400):
+        b = seqgen.from_lists(T, Q, seqgen.SCORING, w, Z)
+        cls = [ga.ga_pair_class(int(n), int(m), w) for n, m in zip(b.t_len, b.q_len)]
+        _say(f"sliding w={w} Z={Z}: classes {sorted(set(cls))}")
+        if w < 0 or w >= 300:
+            assert {5, 6} & set(cls)
+        want, _ = oracle_align(b)
+        assert_same(gpu_align(b), want, b, f"sliding w={w} Z={Z}")
