@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ont",
                     help="ont (the headline batch, default), longread or mixed")
+    ap.add_argument("--schedule", choices=["persistent", "bucketed"], default="persistent",
+                    help="persistent (default) or the plain per-length-bucket launches, for comparison")
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs (profiling runs only)")
     ap.add_argument("--cpu-sample", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -129,6 +131,7 @@ def main():
     log(f"generating workload '{args.workload}'")
     batch = seqgen.make_config(wid, n_pairs=args.pairs)
     ctx = ga.Context(0)
+    ctx.set_schedule(args.schedule)
     packed = ga.pack_batch(ctx, batch)
     out = torch.empty((batch.n_pairs, 7), dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
@@ -209,7 +212,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": wdesc,
+        "config": {"workload": wdesc, "schedule": args.schedule,
                    "pairs": batch.n_pairs, "w": batch.w, "Z": batch.zdrop,
                    "cells": total_cells, "zdropped": int(res[:, 6].sum())},
         "pairs_per_s": round(pairs_per_s, 1),

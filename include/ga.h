@@ -120,13 +120,30 @@ int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
 int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
                    int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);
 
+/* Work schedules of ga_align_batch (results are identical under both):
+ * GA_SCHED_PERSISTENT (the default): every pair goes to the cheapest kernel
+ * class that runs it, ordered longest first within the class, and each
+ * class runs as one persistent launch of resident workgroups pulling pairs
+ * through an atomic head (Section 4.4's load balancing, in this form).
+ * GA_SCHED_BUCKETED: the plain baseline kept for comparison -- pairs are
+ * bucketed by the power of two above max(n, m), and each bucket runs as one
+ * fixed-shape launch (the fixed class holding the bucket's longest band)
+ * with one workgroup per pair; the host waits for the bucket sizes. */
+#define GA_SCHED_PERSISTENT 0
+#define GA_SCHED_BUCKETED 1
+
+/* Select the schedule of later ga_align_batch calls on this context;
+ * GA_EINVAL for an unknown schedule. */
+int ga_context_set_schedule(ga_context_t *ctx, int schedule);
+
 /* Stage timing for benchmarking: while enabled, ga_align_batch records HIP
  * events on its stream around its stages. */
 int ga_context_set_timing(ga_context_t *ctx, int enable);
 
 /* Milliseconds spent by the stages of the last timed ga_align_batch on this
  * context (waits for those events): ms[0] = unpack + planning kernels,
- * ms[1+c] = the alignment kernel of class c, for c < n-1 and c < 11. Class
+ * ms[1+c] = the alignment launches of class c (summed over buckets under
+ * GA_SCHED_BUCKETED), for c < n-1 and c < 11. Class
  * c runs K slots per lane and W waves per pair: (K, W) = (4,1) (8,1) (16,1)
  * (24,1) (32,1) hold bands of up to 64*K*W diagonals; (8,1) (16,1) with a
  * sliding window run pairs whose shorter sequence s has 2s + 11 + K <= 64K

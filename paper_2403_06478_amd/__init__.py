@@ -31,7 +31,11 @@ RESULT_FIELDS = ("max_score", "max_i", "max_j", "end_score", "end_i", "end_j", "
 ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "ga_strerror",
                "ga_pack_words", "ga_pack", "ga_align_batch", "ga_count_cells",
                "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
-               "ga_calibrate_valu")
+               "ga_calibrate_valu", "ga_context_set_schedule")
+
+GA_SCHED_PERSISTENT = 0
+GA_SCHED_BUCKETED = 1
+SCHEDULES = {"persistent": GA_SCHED_PERSISTENT, "bucketed": GA_SCHED_BUCKETED}
 
 # Alignment kernels by class: (slots per lane K, waves per pair, sliding
 # window). A fixed class holds bands of up to 64 * K * waves diagonals; a
@@ -108,6 +112,8 @@ def load_library() -> ctypes.CDLL:
     lib.ga_context_timing.restype = ctypes.c_int
     lib.ga_calibrate_valu.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.ga_calibrate_valu.restype = ctypes.c_int
+    lib.ga_context_set_schedule.argtypes = [vp, ctypes.c_int]
+    lib.ga_context_set_schedule.restype = ctypes.c_int
     lib.ga_pair_class.argtypes = [i32, i32, i32]
     lib.ga_pair_class.restype = ctypes.c_int
     _lib = lib
@@ -167,6 +173,10 @@ class Context:
         ms = (ctypes.c_float * n)()
         _check(load_library().ga_context_timing(self._h, ms, n), "ga_context_timing")
         return [float(x) for x in ms]
+
+    def set_schedule(self, schedule: str):
+        """'persistent' (default) or 'bucketed' (the plain per-length-bucket baseline)."""
+        _check(load_library().ga_context_set_schedule(self._h, SCHEDULES[schedule]), "ga_context_set_schedule")
 
     def calibrate_valu(self, stream=None) -> float:
         """Measured int32 VALU lane-ops per second of this device."""

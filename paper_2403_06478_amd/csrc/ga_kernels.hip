@@ -97,10 +97,27 @@ __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *s
     return -1;
 }
 
-// Device counters (per call): [0..11) class list sizes, [11..22) class heads.
-// They sit right before the planning histogram in the workspace.
+// Work groups of one call: the kernel classes (persistent schedule) or the
+// power-of-two length buckets (bucketed schedule). Device counters per call:
+// [0..32) group list sizes, [32..64) group heads, [64..96) group list starts
+// in the one pair list. They sit right before the planning histogram.
+constexpr int NGROUP = 32;
 constexpr int CNT_COUNT = 0;
-constexpr int CNT_HEAD = NCLASS;
+constexpr int CNT_HEAD = NGROUP;
+constexpr int CNT_START = 2 * NGROUP;
+constexpr int CNT_WORDS = 3 * NGROUP;
+
+// The fixed class a power-of-two length bucket b (max(n, m) < 2^b) runs in
+// under the bucketed schedule: the first fixed class holding the band of two
+// sequences of length 2^b - 1 (-1 if none).
+__host__ __device__ inline int bucket_class(int b, int64_t w) {
+    const int64_t L = ((int64_t)1 << b) - 1;
+    const int64_t half = w >= 0 && w < L ? w : L;
+    const int64_t D = 2 * half + 1;
+    for (int c = 0; c < NCLASS; ++c)
+        if (!class_slides(c) && D <= class_cap(c)) return c;
+    return -1;
+}
 
 // Scores are held in a frame that drifts by the piece-1 extension e per
 // anti-diagonal: a value V of a cell on anti-diagonal r is stored as
@@ -119,10 +136,10 @@ struct DpArgs {
     const int64_t *q_off;
     const int32_t *t_len;
     const int32_t *q_len;
-    const int32_t *list;  // this class's pair list
+    const int32_t *list;  // the pair list of all groups
     int32_t *counters;
     ga_result_t *out;
-    int32_t cls;
+    int32_t group;        // this launch's work group
     int32_t w, Z;
     int32_t q1, c2, d2, e1, e2;
     int32_t oe1, oe2;
@@ -979,27 +996,30 @@ struct Occ {
     static constexpr int value = K <= 8 ? 4 : (K <= 16 && !SL ? 3 : 2);
 };
 
-// Persistent kernel: each workgroup of NW waves takes pairs of its class from
-// the cost-ordered list through an atomic head until the list is exhausted.
+// Each workgroup of NW waves takes pairs of its group from the list through
+// an atomic head until the group is exhausted: persistent (a grid of
+// resident workgroups over a cost-ordered list) or one workgroup per pair
+// (the bucketed schedule).
 template <int K, int NW, bool SL>
 __global__ __launch_bounds__(WAVE * NW, (Occ<K, SL>::value)) void ga_dp_kernel(DpArgs P) {
     __shared__ PairLds<K, NW> S;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int count = P.counters[CNT_COUNT + P.cls];
+    const int count = P.counters[CNT_COUNT + P.group];
+    const int32_t *list = P.list + P.counters[CNT_START + P.group];
     for (;;) {
         int idx = 0;
         if constexpr (NW == 1) {
-            if (lane == 0) idx = atomicAdd(&P.counters[CNT_HEAD + P.cls], 1);
+            if (lane == 0) idx = atomicAdd(&P.counters[CNT_HEAD + P.group], 1);
             idx = __builtin_amdgcn_readfirstlane(idx);
         } else {
-            if (threadIdx.x == 0) S.idx = atomicAdd(&P.counters[CNT_HEAD + P.cls], 1);
+            if (threadIdx.x == 0) S.idx = atomicAdd(&P.counters[CNT_HEAD + P.group], 1);
             __syncthreads();
             idx = __builtin_amdgcn_readfirstlane(S.idx);
             __syncthreads();  // every wave has read S.idx before the next pair overwrites it
         }
         if (idx >= count) break;
-        const int p = P.list[idx];
+        const int p = list[idx];
         align_pair<K, NW, SL>(P, p, lane, wv, S);
     }
 }
@@ -1071,9 +1091,9 @@ __global__ void ga_unpack(const uint32_t *words, const uint32_t *nmask, int64_t 
 // waves then finish on short pairs instead of waiting on one long straggler.
 // Counting sort over cost buckets of PLAN_SHIFT anti-diagonals: classify and
 // histogram, an exclusive scan in descending bucket order, then a scatter.
-constexpr int PLAN_BUCKETS = 4096;  // per class; the last bucket takes every longer pair
+constexpr int PLAN_BUCKETS = 4096;  // per group; the last bucket takes every longer pair
 constexpr int PLAN_SHIFT = 5;
-constexpr int PLAN_BINS = NCLASS * PLAN_BUCKETS;
+constexpr int PLAN_BINS = NGROUP * PLAN_BUCKETS;
 
 struct PlanArgs {
     int64_t n_pairs;
@@ -1082,18 +1102,21 @@ struct PlanArgs {
     int64_t t_nwords, q_nwords;
     int32_t max_len;
     int32_t w;
+    int32_t bucketed;  // schedule: 0 persistent, 1 bucketed
     int32_t *counters;
-    int32_t *hist;    // [PLAN_BINS] pairs per (class, bucket)
-    int32_t *cursor;  // [PLAN_BINS] next list position per (class, bucket)
-    int32_t *keys;    // [n_pairs] class * PLAN_BUCKETS + bucket, or -1 when finished here
-    int32_t *lists;   // NCLASS lists of n_pairs entries
+    int32_t *hist;    // [PLAN_BINS] pairs per (group, cost bucket)
+    int32_t *cursor;  // [PLAN_BINS] next list position per (group, cost bucket)
+    int32_t *keys;    // [n_pairs] group * PLAN_BUCKETS + cost bucket, or -1 when finished here
+    int32_t *lists;   // [n_pairs] the pairs, grouped
     int32_t *err;
     ga_result_t *out;
 };
 
 // Validate each pair, finish invalid and empty pairs, and give the rest a
-// (slot class, cost bucket) key: the class is the smallest slot count that
-// holds the pair's diagonals.
+// (group, cost bucket) key. Persistent schedule: the group is the cheapest
+// class that runs the pair (class_for) and the cost bucket orders each group
+// longest first. Bucketed schedule: the group is the power-of-two bucket of
+// max(n, m), with no ordering inside it.
 __global__ void ga_plan_classify(PlanArgs A) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= A.n_pairs) return;
@@ -1108,35 +1131,35 @@ __global__ void ga_plan_classify(PlanArgs A) {
     } else if (n == 0 || m == 0) {
         A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, 0};
     } else {
-        int a0, a1;
-        if (A.w >= 0) {
-            a0 = max(-A.w, -m);
-            a1 = min(A.w, n);
+        int group, bucket = 0;
+        if (A.bucketed) {
+            group = 32 - __clz((unsigned)max(n, m));  // max(n, m) < 2^group
+            if (bucket_class(group, A.w) < 0) group = -1;
         } else {
-            a0 = -m;
-            a1 = n;
+            int slide;
+            group = class_for(n, m, A.w, &slide);
+            bucket = min((n + m) >> PLAN_SHIFT, PLAN_BUCKETS - 1);
         }
-        int slide;
-        const int cls = class_for(n, m, A.w, &slide);
-        if (cls < 0) {
+        if (group < 0) {
             atomicOr(A.err, 2);
             A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
         } else {
-            const int bucket = min((n + m) >> PLAN_SHIFT, PLAN_BUCKETS - 1);
-            key = cls * PLAN_BUCKETS + bucket;
+            key = group * PLAN_BUCKETS + bucket;
             atomicAdd(&A.hist[key], 1);
         }
     }
     A.keys[p] = key;
 }
 
-// One workgroup of 1024 threads: per class, list positions of the buckets in
-// descending cost order (exclusive scan), and the class list sizes.
+// One workgroup of 1024 threads: list positions of every (group, cost
+// bucket), groups in order and cost buckets descending inside a group
+// (exclusive scan), and the groups' sizes and starts.
 __global__ __launch_bounds__(1024) void ga_plan_scan(PlanArgs A) {
     constexpr int PER = PLAN_BUCKETS / 1024;  // buckets per thread, in descending order
     __shared__ int part[1024];
     const int t = threadIdx.x;
-    for (int c = 0; c < NCLASS; ++c) {
+    int start = 0;
+    for (int c = 0; c < NGROUP; ++c) {
         const int *h = A.hist + c * PLAN_BUCKETS;
         // thread t owns descending ranks t*PER .. t*PER+PER-1, i.e. buckets B-1-rank
         int v[PER], sum = 0;
@@ -1153,13 +1176,18 @@ __global__ __launch_bounds__(1024) void ga_plan_scan(PlanArgs A) {
             part[t] += x;
             __syncthreads();
         }
-        int run = part[t] - sum;
+        int run = start + part[t] - sum;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             A.cursor[c * PLAN_BUCKETS + PLAN_BUCKETS - 1 - (t * PER + k)] = run;
             run += v[k];
         }
-        if (t == 1023) A.counters[CNT_COUNT + c] = part[1023];
+        const int total = part[1023];
+        if (t == 1023) {
+            A.counters[CNT_COUNT + c] = total;
+            A.counters[CNT_START + c] = start;
+        }
+        start += total;
         __syncthreads();
     }
 }
@@ -1169,9 +1197,8 @@ __global__ void ga_plan_scatter(PlanArgs A) {
     if (p >= A.n_pairs) return;
     const int key = A.keys[p];
     if (key < 0) return;
-    const int cls = key / PLAN_BUCKETS;
     const int pos = atomicAdd(&A.cursor[key], 1);
-    A.lists[cls * A.n_pairs + pos] = (int32_t)p;
+    A.lists[pos] = (int32_t)p;
 }
 
 // ---- packing: ASCII -> 2-bit stream + N bitmap (input packing, Section 2.2)
@@ -1248,7 +1275,7 @@ __global__ void ga_pack_kernel(const uint8_t *ascii, const int64_t *off, const i
 
 // --------------------------------------------------------------- host side
 
-constexpr int NEVENTS = 2 + NCLASS;
+constexpr int NEVENTS = 2 + NGROUP;
 
 struct ga_context {
     int device;
@@ -1259,6 +1286,10 @@ struct ga_context {
     int32_t *d_err;    // device error latch
     int timing;        // record stage events in ga_align_batch
     int timed_last;    // the last ga_align_batch recorded them
+    int schedule;      // GA_SCHED_PERSISTENT or GA_SCHED_BUCKETED
+    int n_launch_last;              // launches of the last timed call
+    int launch_class[NGROUP];       // their kernel classes
+    int32_t *h_counts;              // pinned host copy of the group sizes (bucketed schedule)
     hipEvent_t ev[NEVENTS];
 };
 
@@ -1297,6 +1328,22 @@ struct SetDevice {
 template <int K, int NW, bool SL>
 void launch_dp(const DpArgs &a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((ga_dp_kernel<K, NW, SL>), dim3(grid), dim3(WAVE * NW), 0, s, a);
+}
+
+void launch_class(int c, const DpArgs &a, int grid, hipStream_t s) {
+    switch (c) {
+    case 0: launch_dp<4, 1, false>(a, grid, s); break;
+    case 1: launch_dp<8, 1, false>(a, grid, s); break;
+    case 2: launch_dp<16, 1, false>(a, grid, s); break;
+    case 3: launch_dp<24, 1, false>(a, grid, s); break;
+    case 4: launch_dp<32, 1, false>(a, grid, s); break;
+    case 5: launch_dp<8, 1, true>(a, grid, s); break;
+    case 6: launch_dp<16, 1, true>(a, grid, s); break;
+    case 7: launch_dp<24, 2, false>(a, grid, s); break;
+    case 8: launch_dp<32, 2, false>(a, grid, s); break;
+    case 9: launch_dp<32, 3, false>(a, grid, s); break;
+    default: launch_dp<32, 4, false>(a, grid, s); break;
+    }
 }
 
 template <int K, int NW, bool SL>
@@ -1373,6 +1420,7 @@ int ga_context_destroy(ga_context_t *ctx) {
         for (int k = 0; k < NEVENTS; ++k) hipEventDestroy(ctx->ev[k]);
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->d_err) hipFree(ctx->d_err);
+    if (ctx->h_counts) hipHostFree(ctx->h_counts);
     free(ctx);
     return GA_OK;
 }
@@ -1406,12 +1454,22 @@ int ga_context_timing(ga_context_t *ctx, float *ms, int n) {
     if (!ctx || !ms || n < 1) return GA_EINVAL;
     if (!ctx->timed_last) return GA_EINVAL;
     SetDevice sd(ctx->device);
-    if (hipEventSynchronize(ctx->ev[NEVENTS - 1]) != hipSuccess) return GA_EHIP;
-    for (int k = 0; k < n && k < NEVENTS - 1; ++k) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, ctx->ev[k], ctx->ev[k + 1]) != hipSuccess) return GA_EHIP;
-        ms[k] = t;
+    if (hipEventSynchronize(ctx->ev[1 + ctx->n_launch_last]) != hipSuccess) return GA_EHIP;
+    for (int k = 0; k < n; ++k) ms[k] = 0.f;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]) != hipSuccess) return GA_EHIP;
+    ms[0] = t;
+    for (int l = 0; l < ctx->n_launch_last; ++l) {
+        if (hipEventElapsedTime(&t, ctx->ev[1 + l], ctx->ev[2 + l]) != hipSuccess) return GA_EHIP;
+        const int c = ctx->launch_class[l];
+        if (1 + c < n) ms[1 + c] += t;
     }
+    return GA_OK;
+}
+
+int ga_context_set_schedule(ga_context_t *ctx, int schedule) {
+    if (!ctx || (schedule != GA_SCHED_PERSISTENT && schedule != GA_SCHED_BUCKETED)) return GA_EINVAL;
+    ctx->schedule = schedule;
     return GA_OK;
 }
 
@@ -1542,11 +1600,11 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     hipStream_t s = (hipStream_t)stream;
     const int64_t np = bt->n_pairs;
     const size_t off_cnt = 0;
-    const size_t off_hist = 256;
+    const size_t off_hist = align_up(sizeof(int32_t) * CNT_WORDS, 256);
     const size_t off_cursor = off_hist + sizeof(int32_t) * PLAN_BINS;
     const size_t off_keys = off_cursor + sizeof(int32_t) * PLAN_BINS;
     const size_t off_lists = align_up(off_keys + sizeof(int32_t) * (size_t)np, 256);
-    const size_t off_tb = align_up(off_lists + sizeof(int32_t) * NCLASS * (size_t)np, 256);
+    const size_t off_tb = align_up(off_lists + sizeof(int32_t) * (size_t)np, 256);
     const size_t tb_size = align_up(16 * (size_t)bt->t_nwords + 2 * PADB, 256);
     const size_t off_qb = off_tb + tb_size;
     const size_t qb_size = align_up(16 * (size_t)bt->q_nwords + 2 * PADB, 256);
@@ -1584,6 +1642,7 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     pa.q_nwords = bt->q_nwords;
     pa.max_len = bt->max_len;
     pa.w = w;
+    pa.bucketed = ctx->schedule == GA_SCHED_BUCKETED ? 1 : 0;
     pa.counters = counters;
     pa.hist = (int32_t *)(ws + off_hist);
     pa.cursor = (int32_t *)(ws + off_cursor);
@@ -1622,26 +1681,45 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         da.lut_lo = A | (B << 8) | (B << 16) | (B << 24);
         da.lut_hi = N | (N << 8) | (N << 16) | (N << 24);
     }
-    for (int c = 0; c < NCLASS; ++c) {
-        const int64_t want = (int64_t)ctx->num_cu * ctx->blocks_per_cu[c];
-        const int grid = (int)(np < want ? np : want);
-        da.cls = c;
-        da.list = lists + (size_t)c * np;
-        switch (c) {
-        case 0: launch_dp<4, 1, false>(da, grid, s); break;
-        case 1: launch_dp<8, 1, false>(da, grid, s); break;
-        case 2: launch_dp<16, 1, false>(da, grid, s); break;
-        case 3: launch_dp<24, 1, false>(da, grid, s); break;
-        case 4: launch_dp<32, 1, false>(da, grid, s); break;
-        case 5: launch_dp<8, 1, true>(da, grid, s); break;
-        case 6: launch_dp<16, 1, true>(da, grid, s); break;
-        case 7: launch_dp<24, 2, false>(da, grid, s); break;
-        case 8: launch_dp<32, 2, false>(da, grid, s); break;
-        case 9: launch_dp<32, 3, false>(da, grid, s); break;
-        default: launch_dp<32, 4, false>(da, grid, s); break;
+    da.list = lists;
+    int nl = 0;
+    if (ctx->schedule == GA_SCHED_BUCKETED) {
+        // plain per-length-bucket launches, for comparison: wait for the
+        // group sizes, then one fixed-shape launch per non-empty bucket with
+        // one workgroup per pair
+        if (!ctx->h_counts) {
+            if (hipHostMalloc((void **)&ctx->h_counts, sizeof(int32_t) * NGROUP) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->h_counts = nullptr;
+                return GA_ENOMEM;
+            }
         }
-        if (timed) hipEventRecord(ctx->ev[2 + c], s);
+        if (hipMemcpyAsync(ctx->h_counts, counters + CNT_COUNT, sizeof(int32_t) * NGROUP, hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return GA_EHIP;
+        for (int g = 0; g < NGROUP; ++g) {
+            const int cnt = ctx->h_counts[g];
+            const int c = cnt > 0 ? bucket_class(g, w) : -1;
+            if (c < 0) continue;
+            da.group = g;
+            launch_class(c, da, cnt, s);
+            ctx->launch_class[nl] = c;
+            ++nl;
+            if (timed) hipEventRecord(ctx->ev[1 + nl], s);
+        }
+    } else {
+        for (int c = 0; c < NCLASS; ++c) {
+            const int64_t want = (int64_t)ctx->num_cu * ctx->blocks_per_cu[c];
+            const int grid = (int)(np < want ? np : want);
+            da.group = c;
+            launch_class(c, da, grid, s);
+            ctx->launch_class[nl] = c;
+            ++nl;
+            if (timed) hipEventRecord(ctx->ev[1 + nl], s);
+        }
     }
+    ctx->n_launch_last = nl;
     return hipGetLastError() == hipSuccess ? GA_OK : GA_EHIP;
 }
 

@@ -25,6 +25,9 @@ Workload recipes (target = reference, query = mutated target):
 * ``cfg4``  20k HiFi-like pairs, target length U{10000..25000}, 1% errors
   (1:1:1) plus U{1,2,3} long indels of U{50..500} bases each (insertion of
   random bases or deletion, probability 1/2 each); band 2000, z-drop 5000.
+* ``cfg5``  serving requests, one pair each, in request order: with
+  probability 0.95 drawn as in cfg1, else as in cfg4; band 500, z-drop 400
+  for every request. Arrival times are drawn by the serving benchmark.
 
 Point errors: each target base independently is an error with the stated
 rate; a substitution draws one of the three other bases uniformly, an
@@ -190,12 +193,55 @@ def _finish(t_seq, t_lens, q_seq, q_lens, w, zdrop, name):
                      dict(SCORING), int(w), int(zdrop), name)
 
 
-CONFIG_PAIRS = {1: 500, 2: 100_000, 3: 1_000_000, 4: 20_000}
-CONFIG_BAND = {1: (500, 400), 2: (751, 400), 3: (751, 400), 4: (2000, 5000)}
+CONFIG_PAIRS = {1: 500, 2: 100_000, 3: 1_000_000, 4: 20_000, 5: 20_000}
+CONFIG_BAND = {1: (500, 400), 2: (751, 400), 3: (751, 400), 4: (2000, 5000), 5: (500, 400)}
+
+
+def _cfg1_pairs(rng, P):
+    tl = rng.integers(100, 1001, size=P)
+    t = _random_bases(rng, int(tl.sum()))
+    q, ql = _mutate(rng, t, tl, 0.05, (2, 1, 1))
+    return t, tl, q, ql
+
+
+def _cfg4_pairs(rng, P):
+    tl = rng.integers(10000, 25001, size=P)
+    t = _random_bases(rng, int(tl.sum()))
+    q, ql = _mutate(rng, t, tl, 0.01, (1, 1, 1))
+    n_events = rng.integers(1, 4, size=P)
+    for k in range(3):
+        which = n_events > k
+        is_ins = rng.random(P) < 0.5
+        q, ql = _splice(rng, q, ql, which & is_ins, 50, 500, "ins")
+        q, ql = _splice(rng, q, ql, which & ~is_ins, 50, 500, "del")
+    return t, tl, q, ql
+
+
+def _interleave(parts, which):
+    """Pairs in request order: request k comes from parts[which[k]], each
+    part consumed in its own order."""
+    seqs = {"t": [], "q": []}
+    pos = [0] * len(parts)
+    offs = []
+    for t, tl, q, ql in parts:
+        offs.append((_offsets(np.asarray(tl)), _offsets(np.asarray(ql))))
+    tl_out, ql_out = [], []
+    for k in which:
+        t, tl, q, ql = parts[k]
+        i = pos[k]
+        pos[k] += 1
+        to, qo = offs[k][0][i], offs[k][1][i]
+        seqs["t"].append(t[to:to + tl[i]])
+        seqs["q"].append(q[qo:qo + ql[i]])
+        tl_out.append(int(tl[i]))
+        ql_out.append(int(ql[i]))
+    t_all = np.concatenate(seqs["t"]) if seqs["t"] else np.zeros(0, np.uint8)
+    q_all = np.concatenate(seqs["q"]) if seqs["q"] else np.zeros(0, np.uint8)
+    return t_all, np.array(tl_out), q_all, np.array(ql_out)
 
 
 def make_config(config_id: int, n_pairs: Optional[int] = None, seed: int = 0) -> PairBatch:
-    """Draw workload ``config_id`` (1..4). ``n_pairs`` truncates the draw to a
+    """Draw workload ``config_id`` (1..5). ``n_pairs`` truncates the draw to a
     prefix-sized batch with the same distribution (a smaller sample)."""
     if config_id not in CONFIG_PAIRS:
         raise ValueError(f"unknown config {config_id}")
@@ -204,9 +250,16 @@ def make_config(config_id: int, n_pairs: Optional[int] = None, seed: int = 0) ->
     w, zdrop = CONFIG_BAND[config_id]
     name = f"cfg{config_id}" + ("" if n_pairs is None else f"[{P}]")
     if config_id == 1:
-        tl = rng.integers(100, 1001, size=P)
-        t = _random_bases(rng, int(tl.sum()))
-        q, ql = _mutate(rng, t, tl, 0.05, (2, 1, 1))
+        t, tl, q, ql = _cfg1_pairs(rng, P)
+        return _finish(t, tl, q, ql, w, zdrop, name)
+    if config_id == 5:
+        # serving requests: 95% drawn like cfg1, 5% cfg4-sized, in a random
+        # request order; band 500 and z-drop 400 shared by every request
+        is_long = rng.random(P) < 0.05
+        n_long = int(is_long.sum())
+        short = _cfg1_pairs(rng, P - n_long)
+        long_ = _cfg4_pairs(rng, n_long)
+        t, tl, q, ql = _interleave([short, long_], is_long.astype(np.int64))
         return _finish(t, tl, q, ql, w, zdrop, name)
     if config_id == 2:
         tl = np.clip(np.round(rng.lognormal(np.log(2000.0), 0.8, size=P)), 1, 20000).astype(np.int64)
@@ -225,15 +278,7 @@ def make_config(config_id: int, n_pairs: Optional[int] = None, seed: int = 0) ->
         q, ql = _splice(rng, q, ql, which, 2000, 5000, "ins")
         return _finish(t, tl, q, ql, w, zdrop, name)
     # config 4
-    tl = rng.integers(10000, 25001, size=P)
-    t = _random_bases(rng, int(tl.sum()))
-    q, ql = _mutate(rng, t, tl, 0.01, (1, 1, 1))
-    n_events = rng.integers(1, 4, size=P)
-    for k in range(3):
-        which = n_events > k
-        is_ins = rng.random(P) < 0.5
-        q, ql = _splice(rng, q, ql, which & is_ins, 50, 500, "ins")
-        q, ql = _splice(rng, q, ql, which & ~is_ins, 50, 500, "del")
+    t, tl, q, ql = _cfg4_pairs(rng, P)
     return _finish(t, tl, q, ql, w, zdrop, name)
 
 

@@ -349,3 +349,48 @@ def test_sliding_window_short_by_long(w):
             assert {5, 6} & set(cls)
         want, _ = oracle_align(b)
         assert_same(gpu_align(b), want, b, f"sliding w={w} Z={Z}")
+
+
+def test_bucketed_schedule_same_results():
+    """The plain per-length-bucket schedule (the comparison baseline) gives
+    the same results as the persistent one, and both match the oracle."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    full = seqgen.make_config(3, n_pairs=3000)
+    idx = np.nonzero(full.t_len <= 6000)[0][:1200]
+    b = full.subset(idx)
+    ctx = ga.Context(0)
+    packed = ga.pack_batch(ctx, b)
+    outs = {}
+    for sched in ("bucketed", "persistent"):
+        ctx.set_schedule(sched)
+        out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+        torch.cuda.synchronize()
+        ctx.check()
+        outs[sched] = out.cpu().numpy()
+        _say(f"schedule {sched}: {b.n_pairs} pairs")
+    assert np.array_equal(outs["bucketed"], outs["persistent"])
+    want, _ = oracle_align(b)
+    assert_same(outs["persistent"], want, b, "schedules")
+    assert ga.load_library().ga_context_set_schedule(ctx._h, 7) == ga.GA_EINVAL
+    ctx.close()
+
+
+def test_serving_isolation():
+    """Continuous batching: requests of the serving mix arrive over time and
+    are served in many overlapping batches; every result equals the oracle's
+    and the same request run alone."""
+    import paper_2403_06478_amd as ga
+    from paper_2403_06478_amd import serve
+    b = seqgen.make_config(5, n_pairs=160, seed=3)
+    arrivals = np.cumsum(np.random.default_rng(31).exponential(1.0 / 3000.0, size=b.n_pairs))
+    res, lat, wall, nb = serve.serve_trace(b, arrivals, slots=3, max_batch_pairs=8)
+    _say(f"served {b.n_pairs} requests in {nb} batches, {wall * 1e3:.1f} ms, p99 {np.percentile(lat, 99) * 1e3:.2f} ms")
+    assert nb > 3
+    assert np.all(lat > 0)
+    want, _ = oracle_align(b)
+    assert_same(res, want, b, "served")
+    for k in range(0, b.n_pairs, 7):
+        alone = gpu_align(b.subset([k]))
+        assert np.array_equal(alone[0], res[k]), (k, alone[0].tolist(), res[k].tolist())
