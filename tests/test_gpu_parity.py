@@ -385,7 +385,9 @@ def test_serving_isolation():
     from paper_2403_06478_amd import serve
     b = seqgen.make_config(5, n_pairs=160, seed=3)
     arrivals = np.cumsum(np.random.default_rng(31).exponential(1.0 / 3000.0, size=b.n_pairs))
-    res, lat, wall, nb = serve.serve_trace(b, arrivals, slots=3, max_batch_pairs=8)
+    res, lat, wall, nb = serve.serve_trace(b, arrivals, slots=2, long_slots=1, max_batch_pairs=8,
+                                           max_batch_bases=6000, long_batch_pairs=8,
+                                           long_batch_bases=40000)
     _say(f"served {b.n_pairs} requests in {nb} batches, {wall * 1e3:.1f} ms, p99 {np.percentile(lat, 99) * 1e3:.2f} ms")
     assert nb > 3
     assert np.all(lat > 0)
