@@ -131,10 +131,27 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_
  * with one workgroup per pair; the host waits for the bucket sizes. */
 #define GA_SCHED_PERSISTENT 0
 #define GA_SCHED_BUCKETED 1
+/* GA_SCHED_UNORDERED: as GA_SCHED_PERSISTENT, but the pairs of a class run in
+ * batch order instead of longest first (the ordering's own effect, for the
+ * long-pair ratio study of Section 5.6, Fig. 12). */
+#define GA_SCHED_UNORDERED 2
 
 /* Select the schedule of later ga_align_batch calls on this context;
  * GA_EINVAL for an unknown schedule. */
 int ga_context_set_schedule(ga_context_t *ctx, int schedule);
+
+/* Restrict the kernel classes (bit c = class c, see ga_context_timing) that
+ * later ga_align_batch calls on this context may use; the default is all
+ * eleven. Each pair takes the cheapest allowed class that runs it in the
+ * shape the cheapest-first rule gives that class (a sliding class only for a
+ * band wider than its window, a class of W waves only for a band that
+ * reaches its last wave: more than 64*K*(W-1) diagonals). A pair that no
+ * allowed class runs gets the result {0,-1,-1,0,-1,-1,-1} and latches
+ * GA_EDEVICE (see ga_context_check). For sensitivity studies of the kernel
+ * shapes (the slice width of Section 5.5 and the subwarp size of Section 5.7 have
+ * their counterparts in the slots per lane and the waves per pair). Returns
+ * GA_EINVAL for an empty mask or bits above class 10. */
+int ga_context_set_classes(ga_context_t *ctx, uint32_t mask);
 
 /* Stage timing for benchmarking: while enabled, ga_align_batch records HIP
  * events on its stream around its stages. */
@@ -160,6 +177,10 @@ int ga_context_timing(ga_context_t *ctx, float *ms, int n);
  * (4, 8, sliding 8, 16, sliding 16, 24, 32), then the multi-wave classes.
  * Host function, for attributing work to the per-class kernels. */
 int ga_pair_class(int32_t n, int32_t m, int32_t w);
+
+/* As ga_pair_class, among the classes of `mask` only (the choice
+ * ga_align_batch makes after ga_context_set_classes(ctx, mask)). */
+int ga_pair_class_in(int32_t n, int32_t m, int32_t w, uint32_t mask);
 
 /* Measured integer VALU peak of the context's device, for rooflines: a
  * probe kernel of independent v_max3_i32 / v_add_u32 chains (8 waves per

@@ -31,11 +31,13 @@ RESULT_FIELDS = ("max_score", "max_i", "max_j", "end_score", "end_i", "end_j", "
 ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "ga_strerror",
                "ga_pack_words", "ga_pack", "ga_align_batch", "ga_count_cells",
                "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
-               "ga_calibrate_valu", "ga_context_set_schedule")
+               "ga_calibrate_valu", "ga_context_set_schedule", "ga_context_set_classes",
+               "ga_pair_class_in")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
-SCHEDULES = {"persistent": GA_SCHED_PERSISTENT, "bucketed": GA_SCHED_BUCKETED}
+GA_SCHED_UNORDERED = 2
+SCHEDULES = {"persistent": GA_SCHED_PERSISTENT, "bucketed": GA_SCHED_BUCKETED, "unordered": GA_SCHED_UNORDERED}
 
 # Alignment kernels by class: (slots per lane K, waves per pair, sliding
 # window). A fixed class holds bands of up to 64 * K * waves diagonals; a
@@ -116,6 +118,10 @@ def load_library() -> ctypes.CDLL:
     lib.ga_context_set_schedule.restype = ctypes.c_int
     lib.ga_pair_class.argtypes = [i32, i32, i32]
     lib.ga_pair_class.restype = ctypes.c_int
+    lib.ga_pair_class_in.argtypes = [i32, i32, i32, ctypes.c_uint32]
+    lib.ga_pair_class_in.restype = ctypes.c_int
+    lib.ga_context_set_classes.argtypes = [vp, ctypes.c_uint32]
+    lib.ga_context_set_classes.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -175,8 +181,16 @@ class Context:
         return [float(x) for x in ms]
 
     def set_schedule(self, schedule: str):
-        """'persistent' (default) or 'bucketed' (the plain per-length-bucket baseline)."""
+        """'persistent' (default), 'unordered' (persistent without the
+        longest-first order) or 'bucketed' (the plain per-length-bucket
+        baseline)."""
         _check(load_library().ga_context_set_schedule(self._h, SCHEDULES[schedule]), "ga_context_set_schedule")
+
+    def set_classes(self, classes=None):
+        """Restrict the kernel classes later calls may use (indices into
+        ``CLASSES``); None allows all."""
+        mask = (1 << len(CLASSES)) - 1 if classes is None else sum(1 << int(c) for c in set(classes))
+        _check(load_library().ga_context_set_classes(self._h, mask), "ga_context_set_classes")
 
     def calibrate_valu(self, stream=None) -> float:
         """Measured int32 VALU lane-ops per second of this device."""
@@ -282,6 +296,12 @@ def ga_align_batch(ctx: Context, packed: PackedBatch, scoring: dict, w: int, Z: 
 
 def ga_pair_class(n: int, m: int, w: int) -> int:
     return int(load_library().ga_pair_class(int(n), int(m), int(w)))
+
+
+def ga_pair_class_in(n: int, m: int, w: int, classes) -> int:
+    """The class ``ga_align_batch`` picks for the pair among ``classes`` only."""
+    mask = sum(1 << int(c) for c in set(classes))
+    return int(load_library().ga_pair_class_in(int(n), int(m), int(w), mask))
 
 
 def ga_count_cells(n: int, m: int, w: int, r_end: int) -> int:

@@ -64,14 +64,20 @@ __host__ __device__ constexpr bool class_slides(int c) { return c == 5 || c == 6
 __host__ __device__ constexpr int class_cap(int c) { return WAVE * class_k(c) * class_nw(c); }
 constexpr int MAX_DIAGONALS = WAVE * 32 * 4;
 
+constexpr uint32_t ALL_CLASSES = (1u << NCLASS) - 1;
+
 // The class a pair runs in, and whether its one wave slides along the band
 // (*slide = -1 down, +1 up, 0 fixed). A band of D diagonals fits class c when
 // D <= 64*K*NW. When one sequence is short, an anti-diagonal's cells from the
 // boundary cell to the cell just past the short sequence's end span at most
 // 2*min(n,m) + 3 diagonals; a single wave whose window follows them (moved
 // one lane at a time, hence the K of slack) runs such a pair even when the
-// whole band would not fit.
-__host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *slide) {
+// whole band would not fit. `mask` restricts the classes considered; a class
+// is then taken only in the shape the cheapest-first rule gives it: a
+// sliding class only for a band wider than its window, a class of NW waves
+// only for a band that reaches its last wave.
+__host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *slide,
+                                         uint32_t mask = ALL_CLASSES) {
     int64_t a0, a1;
     if (w >= 0) {
         a0 = -w > -m ? -w : -m;
@@ -87,9 +93,10 @@ __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *s
     const int order[NCLASS] = {0, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10};
     for (int k = 0; k < NCLASS; ++k) {
         const int c = order[k];
+        if (!((mask >> c) & 1u)) continue;
         if (!class_slides(c)) {
-            if (D <= class_cap(c)) return c;
-        } else if (span + class_k(c) <= class_cap(c)) {
+            if (D <= class_cap(c) && D > WAVE * class_k(c) * (class_nw(c) - 1)) return c;
+        } else if (D > class_cap(c) && span + class_k(c) <= class_cap(c)) {
             *slide = n <= m ? -1 : 1;
             return c;
         }
@@ -110,12 +117,12 @@ constexpr int CNT_WORDS = 3 * NGROUP;
 // The fixed class a power-of-two length bucket b (max(n, m) < 2^b) runs in
 // under the bucketed schedule: the first fixed class holding the band of two
 // sequences of length 2^b - 1 (-1 if none).
-__host__ __device__ inline int bucket_class(int b, int64_t w) {
+__host__ __device__ inline int bucket_class(int b, int64_t w, uint32_t mask = ALL_CLASSES) {
     const int64_t L = ((int64_t)1 << b) - 1;
     const int64_t half = w >= 0 && w < L ? w : L;
     const int64_t D = 2 * half + 1;
     for (int c = 0; c < NCLASS; ++c)
-        if (!class_slides(c) && D <= class_cap(c)) return c;
+        if (((mask >> c) & 1u) && !class_slides(c) && D <= class_cap(c)) return c;
     return -1;
 }
 
@@ -1103,6 +1110,8 @@ struct PlanArgs {
     int32_t max_len;
     int32_t w;
     int32_t bucketed;  // schedule: 0 persistent, 1 bucketed
+    int32_t ordered;   // persistent: order each class longest first
+    uint32_t mask;     // kernel classes allowed
     int32_t *counters;
     int32_t *hist;    // [PLAN_BINS] pairs per (group, cost bucket)
     int32_t *cursor;  // [PLAN_BINS] next list position per (group, cost bucket)
@@ -1134,11 +1143,11 @@ __global__ void ga_plan_classify(PlanArgs A) {
         int group, bucket = 0;
         if (A.bucketed) {
             group = 32 - __clz((unsigned)max(n, m));  // max(n, m) < 2^group
-            if (bucket_class(group, A.w) < 0) group = -1;
+            if (bucket_class(group, A.w, A.mask) < 0) group = -1;
         } else {
             int slide;
-            group = class_for(n, m, A.w, &slide);
-            bucket = min((n + m) >> PLAN_SHIFT, PLAN_BUCKETS - 1);
+            group = class_for(n, m, A.w, &slide, A.mask);
+            bucket = A.ordered ? min((n + m) >> PLAN_SHIFT, PLAN_BUCKETS - 1) : 0;
         }
         if (group < 0) {
             atomicOr(A.err, 2);
@@ -1286,7 +1295,8 @@ struct ga_context {
     int32_t *d_err;    // device error latch
     int timing;        // record stage events in ga_align_batch
     int timed_last;    // the last ga_align_batch recorded them
-    int schedule;      // GA_SCHED_PERSISTENT or GA_SCHED_BUCKETED
+    int schedule;      // GA_SCHED_*
+    uint32_t class_mask;  // kernel classes the planner may use
     int n_launch_last;              // launches of the last timed call
     int launch_class[NGROUP];       // their kernel classes
     int32_t *h_counts;              // pinned host copy of the group sizes (bucketed schedule)
@@ -1384,6 +1394,7 @@ int ga_context_create(ga_context_t **out, int device) {
     ga_context *ctx = (ga_context *)calloc(1, sizeof(ga_context));
     if (!ctx) return GA_ENOMEM;
     ctx->device = device;
+    ctx->class_mask = ALL_CLASSES;
     if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         ctx->num_cu = 256;
     // persistent grids: as many workgroups as the registers let reside
@@ -1468,23 +1479,29 @@ int ga_context_timing(ga_context_t *ctx, float *ms, int n) {
 }
 
 int ga_context_set_schedule(ga_context_t *ctx, int schedule) {
-    if (!ctx || (schedule != GA_SCHED_PERSISTENT && schedule != GA_SCHED_BUCKETED)) return GA_EINVAL;
+    if (!ctx || (schedule != GA_SCHED_PERSISTENT && schedule != GA_SCHED_BUCKETED &&
+                 schedule != GA_SCHED_UNORDERED))
+        return GA_EINVAL;
     ctx->schedule = schedule;
+    return GA_OK;
+}
+
+int ga_context_set_classes(ga_context_t *ctx, uint32_t mask) {
+    if (!ctx || mask == 0 || (mask & ~ALL_CLASSES) != 0) return GA_EINVAL;
+    ctx->class_mask = mask;
     return GA_OK;
 }
 
 int ga_pair_class(int32_t n, int32_t m, int32_t w) {
     if (n <= 0 || m <= 0) return -1;
-    int64_t a0, a1;
-    if (w >= 0) {
-        a0 = -w > -m ? -w : -m;
-        a1 = w < n ? w : n;
-    } else {
-        a0 = -m;
-        a1 = n;
-    }
     int slide;
     return class_for(n, m, w, &slide);
+}
+
+int ga_pair_class_in(int32_t n, int32_t m, int32_t w, uint32_t mask) {
+    if (n <= 0 || m <= 0) return -1;
+    int slide;
+    return class_for(n, m, w, &slide, mask & ALL_CLASSES);
 }
 
 int64_t ga_pack_words(const int32_t *len_host, int64_t n) {
@@ -1643,6 +1660,8 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     pa.max_len = bt->max_len;
     pa.w = w;
     pa.bucketed = ctx->schedule == GA_SCHED_BUCKETED ? 1 : 0;
+    pa.ordered = ctx->schedule == GA_SCHED_PERSISTENT ? 1 : 0;
+    pa.mask = ctx->class_mask;
     pa.counters = counters;
     pa.hist = (int32_t *)(ws + off_hist);
     pa.cursor = (int32_t *)(ws + off_cursor);
@@ -1700,7 +1719,7 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
             return GA_EHIP;
         for (int g = 0; g < NGROUP; ++g) {
             const int cnt = ctx->h_counts[g];
-            const int c = cnt > 0 ? bucket_class(g, w) : -1;
+            const int c = cnt > 0 ? bucket_class(g, w, ctx->class_mask) : -1;
             if (c < 0) continue;
             da.group = g;
             launch_class(c, da, cnt, s);
@@ -1710,6 +1729,7 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         }
     } else {
         for (int c = 0; c < NCLASS; ++c) {
+            if (!((ctx->class_mask >> c) & 1u)) continue;
             const int64_t want = (int64_t)ctx->num_cu * ctx->blocks_per_cu[c];
             const int grid = (int)(np < want ? np : want);
             da.group = c;

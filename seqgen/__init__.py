@@ -29,6 +29,9 @@ Workload recipes (target = reference, query = mutated target):
   probability 0.95 drawn as in cfg1, else as in cfg4; band 500, z-drop 400
   for every request. Arrival times are drawn by the serving benchmark.
 
+``long_ratio`` (the synthetic study of Section 5.6, Fig. 12): a given
+fraction of 4096-base targets among 128-base ones, 5% errors (1:1:1).
+
 Point errors: each target base independently is an error with the stated
 rate; a substitution draws one of the three other bases uniformly, an
 insertion emits a random base after the original, a deletion drops the base.
@@ -280,6 +283,21 @@ def make_config(config_id: int, n_pairs: Optional[int] = None, seed: int = 0) ->
     # config 4
     t, tl, q, ql = _cfg4_pairs(rng, P)
     return _finish(t, tl, q, ql, w, zdrop, name)
+
+
+def long_ratio(n_pairs: int, frac_long: float, seed: int = 0, long_len: int = 4096,
+               short_len: int = 128, err: float = 0.05, w: int = 751, zdrop: int = 400) -> PairBatch:
+    """The long-pair ratio workload: round(frac_long * n_pairs) pairs with a
+    ``long_len``-base target, the rest ``short_len``, at random positions in
+    the batch; queries carry ``err`` point errors (1:1:1). Drawn from
+    ``numpy.random.default_rng([6, seed])``."""
+    rng = np.random.default_rng([6, seed])
+    n_long = int(round(frac_long * n_pairs))
+    tl = np.full(n_pairs, short_len, dtype=np.int64)
+    tl[rng.permutation(n_pairs)[:n_long]] = long_len
+    t = _random_bases(rng, int(tl.sum()))
+    q, ql = _mutate(rng, t, tl, err, (1, 1, 1))
+    return _finish(t, tl, q, ql, w, zdrop, f"long_ratio[{n_pairs},{frac_long:g}]")
 
 
 def random_pairs(rng: np.random.Generator, n_pairs: int, len_lo: int, len_hi: int,

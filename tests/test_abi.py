@@ -103,3 +103,38 @@ def test_pair_class_rule():
         if got >= 0 and not ga.CLASSES[got][2]:
             k, nw, _ = ga.CLASSES[got]
             assert D <= 64 * k * nw
+
+
+def test_pair_class_rule_restricted():
+    """Class choice among a subset of the kernels: the cheapest allowed class
+    that runs the pair in the shape the full rule gives it (a sliding class
+    only for a band wider than its window, W waves only for a band reaching
+    the last wave). With every class allowed these extra conditions never
+    bind, so the choice is the full rule's."""
+    import numpy as np
+
+    import paper_2403_06478_amd as ga
+    rng = np.random.default_rng(6)
+    order = [0, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10]
+    every = range(len(ga.CLASSES))
+    for _ in range(3000):
+        n, m = (int(x) for x in rng.integers(1, 9000, 2))
+        w = int(rng.choice([-1, 0, 100, 300, 751, 1000, 1500, 2500, 3500, 5000]))
+        assert ga.ga_pair_class_in(n, m, w, every) == ga.ga_pair_class(n, m, w)
+        allowed = [c for c in every if rng.random() < 0.4] or [int(rng.integers(0, len(ga.CLASSES)))]
+        a0, a1 = (max(-w, -m), min(w, n)) if w >= 0 else (-m, n)
+        D = a1 - a0 + 1
+        want = -1
+        for c in order:
+            if c not in allowed:
+                continue
+            k, nw, sl = ga.CLASSES[c]
+            cap = 64 * k * nw
+            if sl:
+                ok = D > cap and 2 * min(n, m) + 11 + k <= cap
+            else:
+                ok = 64 * k * (nw - 1) < D <= cap
+            if ok:
+                want = c
+                break
+        assert ga.ga_pair_class_in(n, m, w, allowed) == want, (n, m, w, allowed, want)

@@ -363,7 +363,7 @@ def test_bucketed_schedule_same_results():
     ctx = ga.Context(0)
     packed = ga.pack_batch(ctx, b)
     outs = {}
-    for sched in ("bucketed", "persistent"):
+    for sched in ("bucketed", "unordered", "persistent"):
         ctx.set_schedule(sched)
         out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
         torch.cuda.synchronize()
@@ -371,6 +371,7 @@ def test_bucketed_schedule_same_results():
         outs[sched] = out.cpu().numpy()
         _say(f"schedule {sched}: {b.n_pairs} pairs")
     assert np.array_equal(outs["bucketed"], outs["persistent"])
+    assert np.array_equal(outs["unordered"], outs["persistent"])
     want, _ = oracle_align(b)
     assert_same(outs["persistent"], want, b, "schedules")
     assert ga.load_library().ga_context_set_schedule(ctx._h, 7) == ga.GA_EINVAL
@@ -396,3 +397,94 @@ def test_serving_isolation():
     for k in range(0, b.n_pairs, 7):
         alone = gpu_align(b.subset([k]))
         assert np.array_equal(alone[0], res[k]), (k, alone[0].tolist(), res[k].tolist())
+
+
+def _short_by_long(rng, n_pairs, t_lo, t_hi, q_lo, q_hi, w, Z=400):
+    """Long targets against short queries copied (with 5% substitutions)
+    from a random place of the target."""
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    T, Q = [], []
+    for _ in range(n_pairs):
+        n = int(rng.integers(t_lo, t_hi + 1))
+        m = int(rng.integers(q_lo, q_hi + 1))
+        t = acgt[rng.integers(0, 4, n)]
+        s0 = int(rng.integers(0, n - m + 1))
+        q = t[s0:s0 + m].copy()
+        sub = rng.random(m) < 0.05
+        q[sub] = acgt[rng.integers(0, 4, int(sub.sum()))]
+        T.append(t.tobytes())
+        Q.append(q.tobytes())
+    return seqgen.from_lists(T, Q, seqgen.SCORING, w, Z)
+
+
+def test_every_class_same_results():
+    """The result does not depend on the kernel shape: pairs forced onto each
+    class that runs them (ga_context_set_classes) give the default choice's
+    results, which match the oracle. Covers every class, fixed, sliding and
+    multi-wave, on bands each shape holds."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    rng = np.random.default_rng(41)
+    scenarios = [
+        ("fixed w=100", seqgen.random_pairs(rng, 40, 300, 700, err=0.05, w=100, zdrop=400), [0, 1, 2, 3, 4]),
+        ("sliding K8", _short_by_long(rng, 16, 1500, 2500, 60, 240, 751), [5, 2, 3, 4]),
+        ("sliding K16", _short_by_long(rng, 16, 1500, 2500, 280, 490, 751), [6, 3, 4]),
+        ("w=1000", seqgen.random_pairs(rng, 10, 2200, 2600, err=0.05, w=1000, zdrop=400), [4, 7]),
+        ("w=1500", seqgen.random_pairs(rng, 8, 3200, 3500, err=0.05, w=1500, zdrop=400), [7, 8]),
+        ("w=2500", seqgen.random_pairs(rng, 4, 2700, 3000, err=0.05, w=2500, zdrop=400), [9]),
+        ("w=3500", seqgen.random_pairs(rng, 3, 3600, 3800, err=0.05, w=3500, zdrop=400), [10]),
+    ]
+    ctx = ga.Context(0)
+    for label, b, classes in scenarios:
+        packed = ga.pack_batch(ctx, b)
+        _say(f"classes {label}: default, {b.n_pairs} pairs")
+        ref = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+        torch.cuda.synchronize()
+        ctx.check()
+        ref = ref.cpu().numpy()
+        want, _ = oracle_align(b)
+        assert_same(ref, want, b, label)
+        for c in classes:
+            idx = [p for p in range(b.n_pairs)
+                   if ga.ga_pair_class_in(int(b.t_len[p]), int(b.q_len[p]), b.w, [c]) == c]
+            assert len(idx) >= max(1, b.n_pairs // 2), (label, c, len(idx))
+            sub = b.subset(idx)
+            ctx.set_classes([c])
+            _say(f"classes {label}: {ga.class_name(c)} on {len(idx)} pairs")
+            got = ga.ga_align_batch(ctx, ga.pack_batch(ctx, sub), sub.scoring, sub.w, sub.zdrop)
+            torch.cuda.synchronize()
+            ctx.check()
+            assert_same(got.cpu().numpy(), ref[idx], sub, f"{label} class {c}")
+            ctx.set_classes(None)
+    ctx.close()
+
+
+def test_class_mask_errors():
+    """A pair that no allowed class runs is flagged and latches GA_EDEVICE;
+    the other pairs are unaffected; bad masks are rejected."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    rng = np.random.default_rng(43)
+    b = seqgen.random_pairs(rng, 12, 100, 900, err=0.05, w=300, zdrop=400)
+    ok = np.array([ga.ga_pair_class_in(int(n), int(m), b.w, [0]) == 0 for n, m in zip(b.t_len, b.q_len)])
+    assert ok.any() and not ok.all()
+    ctx = ga.Context(0)
+    lib = ga.load_library()
+    assert lib.ga_context_set_classes(ctx._h, 0) == ga.GA_EINVAL
+    assert lib.ga_context_set_classes(ctx._h, 1 << len(ga.CLASSES)) == ga.GA_EINVAL
+    packed = ga.pack_batch(ctx, b)
+    ctx.set_classes([0])
+    out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+    torch.cuda.synchronize()
+    with pytest.raises(ga.GaError) as ei:
+        ctx.check()
+    assert ei.value.code == ga.GA_EDEVICE
+    got = out.cpu().numpy()
+    assert np.all(got[~ok] == np.array([0, -1, -1, 0, -1, -1, -1]))
+    want, _ = oracle_align(b)
+    assert_same(got[ok], want[ok], b.subset(np.nonzero(ok)[0]), "mask errors")
+    ctx.set_classes(None)
+    ctx.check()
+    ctx.close()
