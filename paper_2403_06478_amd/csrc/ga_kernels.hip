@@ -997,10 +997,12 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
 }
 
 // Waves per SIMD each kernel is compiled for (register budget; a sliding
-// window needs room for the lane shifts).
-template <int K, bool SL>
+// window needs room for the lane shifts). The one-wave K=32 kernel needs
+// more than the 256 registers two waves per SIMD leave it: at one wave per
+// SIMD its excess lives in accumulation registers instead of scratch memory.
+template <int K, int NW, bool SL>
 struct Occ {
-    static constexpr int value = K <= 8 ? 4 : (K <= 16 && !SL ? 3 : 2);
+    static constexpr int value = K <= 8 ? 4 : (K <= 16 && !SL ? 3 : (K == 32 && NW == 1 ? 1 : 2));
 };
 
 // Each workgroup of NW waves takes pairs of its group from the list through
@@ -1008,7 +1010,7 @@ struct Occ {
 // resident workgroups over a cost-ordered list) or one workgroup per pair
 // (the bucketed schedule).
 template <int K, int NW, bool SL>
-__global__ __launch_bounds__(WAVE * NW, (Occ<K, SL>::value)) void ga_dp_kernel(DpArgs P) {
+__global__ __launch_bounds__(WAVE * NW, (Occ<K, NW, SL>::value)) void ga_dp_kernel(DpArgs P) {
     __shared__ PairLds<K, NW> S;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);

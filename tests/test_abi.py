@@ -138,3 +138,25 @@ def test_pair_class_rule_restricted():
                 want = c
                 break
         assert ga.ga_pair_class_in(n, m, w, allowed) == want, (n, m, w, allowed, want)
+
+
+def test_fasta_reader(tmp_path):
+    """FASTA records: multi-line sequences joined, blank lines and inner
+    whitespace dropped, bytes kept as written; data before a header and
+    unequal record counts are errors."""
+    import pytest
+
+    from paper_2403_06478_amd import cli
+    ref = tmp_path / "ref.fa"
+    ref.write_bytes(b">r1 first\nACGT\nacgn\n\n>r2\n\n>r3\nAC GT\r\nTT\n")
+    names, seqs = cli.read_fasta(str(ref))
+    assert names == ["r1 first", "r2", "r3"]
+    assert seqs == [b"ACGTacgn", b"", b"ACGTTT"]
+    bad = tmp_path / "bad.fa"
+    bad.write_bytes(b"ACGT\n>x\nAC\n")
+    with pytest.raises(ValueError):
+        cli.read_fasta(str(bad))
+    qry = tmp_path / "q.fa"
+    qry.write_bytes(b">q1\nACGT\n")
+    with pytest.raises(ValueError):
+        cli.make_batch(str(ref), str(qry), dict(a=2, b=4, q=4, e=2, q2=24, e2=1, ambig=1), 10, 10)

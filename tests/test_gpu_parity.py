@@ -488,3 +488,37 @@ def test_class_mask_errors():
     ctx.set_classes(None)
     ctx.check()
     ctx.close()
+
+
+def test_cli_fasta(tmp_path):
+    """The FASTA front end: wrapped, mixed-case records with N and an empty
+    record, aligned record by record; score.log matches the oracle."""
+    import json
+
+    from paper_2403_06478_amd import cli
+    rng = np.random.default_rng(47)
+    b = seqgen.random_pairs(rng, 30, 0, 700, err=0.08, n_rate=0.01, related=0.9, w=200, zdrop=100)
+    T = [bytes(x if (k % 7) else x | 0x20 for k, x in enumerate(b.target(p))) for p in range(b.n_pairs)]
+    Q = [b.query(p) for p in range(b.n_pairs)]
+    T[3] = b""
+
+    def write(path, seqs, tag):
+        with open(path, "wb") as f:
+            for k, s in enumerate(seqs):
+                f.write(f">{tag}{k} record {k}\n".encode())
+                for o in range(0, len(s), 60):
+                    f.write(s[o:o + 60] + b"\n")
+
+    write(tmp_path / "ref.fa", T, "r")
+    write(tmp_path / "qry.fa", Q, "q")
+    out = tmp_path / "out"
+    _say("cli: 30 records")
+    assert cli.main([str(tmp_path / "ref.fa"), str(tmp_path / "qry.fa"), "-a", "2", "-b", "4", "-q", "4",
+                     "-r", "2", "-z", "100", "-w", "200", "-o", str(out)]) == 0
+    rows = [line.split("\t") for line in (out / "score.log").read_text().splitlines() if not line.startswith("#")]
+    assert [r[0] for r in rows] == [f"r{k} record {k}" for k in range(b.n_pairs)]
+    got = np.array([[int(x) for x in r[2:]] for r in rows], dtype=np.int32)
+    want, _ = oracle_align(seqgen.from_lists(T, Q, seqgen.SCORING, 200, 100))
+    assert_same(got, want, None, "cli")
+    meta = json.loads((out / "time.json").read_text())
+    assert meta["pairs"] == b.n_pairs and meta["kernel_ms"] > 0
