@@ -663,6 +663,13 @@ __device__ __forceinline__ void read_edges(const PairLds<K, NW> &S, int r, int w
 }
 
 
+// Bit T set for every step T of a block (0..7) with lo <= T <= hi.
+__device__ __forceinline__ uint32_t step_bits(int lo, int hi) {
+    lo = max(lo, 0);
+    hi = min(hi, 7);
+    return lo > hi ? 0u : ((0xFFu >> (7 - hi)) & (0xFFu << lo));
+}
+
 // One wave per pair, 8 anti-diagonals r0 .. r0+7. Step T finishes
 // anti-diagonal r-1 (its clamps, lane maxima and wave reduction) in the
 // same straight-line code as the update of anti-diagonal r, so the serial
@@ -679,6 +686,17 @@ template <int K>
 __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
                                            int r0, int lane, uint64_t wall_lanes, int wall_pos,
                                            PairLds<K, 1> &S) {
+    // Which steps of the block need the wall clamp, an exit-cell clamp or
+    // the boundary-cell check, as bit masks over T, worked out once per
+    // block: step T finishes anti-diagonal r0+T-1, whose cell i = n sits at
+    // slot position pi0 - T and whose cell j = m at pj0 + T.
+    const int t1 = 1 - r0;  // first step with an anti-diagonal to finish
+    const int pi0 = 2 * g.n - r0 + 1 - g.a0w;
+    const int pj0 = r0 - 1 - 2 * g.m - g.a0w;
+    const uint32_t bits_i = step_bits(max(max(t1, 2 * g.n - r0 + 1 - g.a1), pi0 - WAVE * K + 1), pi0);
+    const uint32_t bits_j = step_bits(max(max(t1, g.a0 + 2 * g.m + 1 - r0), -pj0), WAVE * K - 1 - pj0);
+    const uint32_t bits_w = wall_lanes != 0 ? ((wall_pos & 1) ? 0x55u : 0xAAu) & step_bits(t1, 7) : 0u;
+    const uint32_t bits_ring = step_bits(t1, max(g.a1, -g.a0) - r0 - 1);
 #define GA_STEP1(T)                                                                        \
     {                                                                                      \
         constexpr int C = (T) & 1;                                                         \
@@ -687,24 +705,16 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
         const int r = r0 + (T);                                                            \
         if (r >= 0) {                                                                      \
             const int rp = r - 1;                                                          \
-            if (r >= 1) {                                                                  \
-                if (wall_lanes != 0 && (wall_pos & 1) == CP)                               \
-                    clamp_wall<K>(st, wall_lanes, wall_pos);                               \
-                const int di = 2 * g.n - rp;  /* i = n on anti-diagonal rp */              \
-                const int pi = di - g.a0w;                                                 \
-                if (di <= g.a1 && pi >= 0 && pi < WAVE * K) clamp_cell<K, true>(st, pi);   \
-                const int dj = rp - 2 * g.m;  /* j = m */                                  \
-                const int pj = dj - g.a0w;                                                 \
-                if (dj >= g.a0 && pj >= 0 && pj < WAVE * K) clamp_cell<K, false>(st, pj); \
-            }                                                                              \
+            if (bits_w & (1u << (T))) clamp_wall<K>(st, wall_lanes, wall_pos);             \
+            if (bits_i & (1u << (T))) clamp_cell<K, true>(st, pi0 - (T));                  \
+            if (bits_j & (1u << (T))) clamp_cell<K, false>(st, pj0 + (T));                 \
             int lm = lane_max<K, CP, 1>(st, g, 0, 0, false);                               \
             int MA = wave_max(lm);                                                         \
             dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                       \
             if (r >= 1) {                                                                  \
                 int vlo = 0, vhi = 0;                                                      \
                 bool mp = false;                                                           \
-                const bool ring = rp + 2 <= g.a1 || -rp - 2 >= g.a0;                       \
-                if (__builtin_expect(ring && MA == ring_a(P, rp), 0)) {                    \
+                if (__builtin_expect((bits_ring & (1u << (T))) && MA == ring_a(P, rp), 0)) { \
                     /* a boundary cell may hold the maximum: redo it masked */             \
                     mp = true;                                                             \
                     diag_window(g, rp, vlo, vhi);                                          \
