@@ -536,7 +536,7 @@ __device__ __forceinline__ int decide(const PairState<K> &st, const DpArgs &P, c
 template <int K, int C, int NW>
 __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArgs &P, const Geo &g,
                                              Track &tr, int r, int lane, int wv, PairLds<K, NW> &S,
-                                             int p) {
+                                             int p, bool ring) {
     // unmasked lane maxima: outside the rectangle only the two boundary
     // cells can be finite (the cells past either end are clamped)
     int lm = lane_max<K, C, NW>(st, g, 0, 0, false);
@@ -561,7 +561,6 @@ __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArg
     const bool last = r >= g.r_last;
     int vlo = 0, vhi = 0;
     bool masked = false;
-    const bool ring = r + 2 <= g.a1 || -r - 2 >= g.a0;
     if (__builtin_expect(ring && MA == ring_a(P, r), 0)) {
         // a boundary cell may hold the maximum: redo the anti-diagonal masked
         masked = true;
@@ -748,6 +747,17 @@ template <int K, int NW>
 __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
                                           Track &tr, int r0, int lane, int wv, uint64_t wall_lanes,
                                           int wall_pos, PairLds<K, NW> &S, int p) {
+    // the steps that need each clamp and the boundary-cell check, as bit
+    // masks over T worked out once per block (step T updates anti-diagonal
+    // r0+T: its cell i = n at slot position pi0 - T of this wave, its cell
+    // j = m at pj0 + T)
+    const int t0 = -r0;
+    const int pi0 = 2 * g.n - r0 - g.a0w;
+    const int pj0 = r0 - 2 * g.m - g.a0w;
+    const uint32_t bits_i = step_bits(max(max(t0, 2 * g.n - r0 - g.a1), pi0 - WAVE * K + 1), pi0);
+    const uint32_t bits_j = step_bits(max(max(t0, g.a0 + 2 * g.m - r0), -pj0), WAVE * K - 1 - pj0);
+    const uint32_t bits_w = wall_lanes != 0 ? ((wall_pos & 1) ? 0xAAu : 0x55u) & step_bits(t0, 7) : 0u;
+    const uint32_t bits_ring = step_bits(t0, max(g.a1, -g.a0) - r0 - 2);
 #define GA_STEP(T)                                                                    \
     {                                                                                 \
         constexpr int C = (T) & 1;                                                    \
@@ -757,17 +767,13 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
             int f0, f1, f2;                                                           \
             read_edges<C, K, NW>(S, r, wv, f0, f1, f2);                               \
             dp_step<K, C, KC>(st, P, f0, f1, f2);                                     \
-            if (wall_lanes != 0 && (wall_pos & 1) == C) clamp_wall<K>(st, wall_lanes, wall_pos); \
-            {   /* cells leaving the rectangle, in the wave holding them */           \
-                const int pi = 2 * g.n - r - g.a0 - wv * (WAVE * K);                  \
-                if (2 * g.n - r <= g.a1 && pi >= 0 && pi < WAVE * K)                  \
-                    clamp_cell<K, true>(st, pi);                                      \
-                const int pj = r - 2 * g.m - g.a0 - wv * (WAVE * K);                  \
-                if (r - 2 * g.m >= g.a0 && pj >= 0 && pj < WAVE * K)                  \
-                    clamp_cell<K, false>(st, pj);                                     \
-            }                                                                         \
+            if (bits_w & (1u << (T))) clamp_wall<K>(st, wall_lanes, wall_pos);        \
+            if (bits_i & (1u << (T))) clamp_cell<K, true>(st, pi0 - (T));             \
+            if (bits_j & (1u << (T))) clamp_cell<K, false>(st, pj0 + (T));            \
             publish_edges<K, C, NW>(st, S, r, lane, wv);                              \
-            if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, S, p)) return true; \
+            if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, S, p,               \
+                                       (bits_ring & (1u << (T))) != 0))               \
+                return true;                                                          \
         }                                                                             \
     }
     GA_STEP(0)
