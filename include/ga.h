@@ -69,7 +69,7 @@ typedef struct {
 typedef struct {
     int64_t n_pairs;
     const uint32_t *t_words_dev; /* target 2-bit stream */
-    int64_t t_nwords;            /* its length in words */
+    int64_t t_nwords;            /* its length in words (may exceed the packed words) */
     const uint32_t *q_words_dev; /* query 2-bit stream */
     int64_t q_nwords;
     const int64_t *t_off_dev;    /* [n_pairs] first word of each target */
@@ -107,7 +107,10 @@ int64_t ga_pack_words(const int32_t *len_host, int64_t n);
  * Writes word_off_dev[p] (exclusive prefix sum of ceil(len/16)), the 2-bit
  * stream words_dev[0 .. ga_pack_words) and the N bitmap
  * nmask_dev[0 .. (ga_pack_words+1)/2). Any byte outside ACGTacgt becomes N
- * (2-bit code 0 plus its N bit). `nwords` must equal ga_pack_words(len). */
+ * (2-bit code 0 plus its N bit). `nwords` is the capacity of words_dev in
+ * words, at least ga_pack_words(len); words past the packed ones are left
+ * as they are (a caller may declare fixed capacities, e.g. to replay one
+ * captured graph over batches of different sizes). */
 int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
             const int32_t *len_dev, int64_t n, int64_t nwords, uint32_t *words_dev,
             int64_t *word_off_dev, uint32_t *nmask_dev, void *stream);
@@ -119,6 +122,12 @@ int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
  * Band widths with 2*min(w, max_len) + 1 > 8192 return GA_EUNSUPPORTED. */
 int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
                    int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);
+/* Graph capture: under GA_SCHED_PERSISTENT (and GA_SCHED_UNORDERED) with
+ * timing off, ga_pack and ga_align_batch only enqueue kernels on `stream`
+ * (no host waits, no memset nodes), so both may be captured into a HIP graph
+ * once the context's workspace has grown to the batch's size: run the same
+ * shapes once before capturing. The graph then holds the pointers, sizes
+ * and parameters of the captured call; pairs of length 0 finish at once. */
 
 /* Work schedules of ga_align_batch (results are identical under both):
  * GA_SCHED_PERSISTENT (the default): every pair goes to the cheapest kernel

@@ -1342,14 +1342,17 @@ int ensure_ws(ga_context *ctx, size_t need) {
     return GA_OK;
 }
 
+// Makes `dev` current for the scope of a call; touches the device setting
+// only when another device is current.
 struct SetDevice {
     int prev = -1;
+    bool changed = false;
     explicit SetDevice(int dev) {
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) hipSetDevice(dev);
+        if (prev != dev) changed = hipSetDevice(dev) == hipSuccess;
     }
     ~SetDevice() {
-        if (prev >= 0) hipSetDevice(prev);
+        if (changed && prev >= 0) hipSetDevice(prev);
     }
 };
 

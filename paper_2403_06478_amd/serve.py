@@ -49,13 +49,28 @@ class _Slot:
     and staging buffers sized once for the largest batch -- pinned host
     buffers for the request bytes and results, device buffers for the packed
     streams -- so a batch allocates nothing (an allocation can synchronise
-    the device and stall every other slot)."""
+    the device and stall every other slot).
 
-    def __init__(self, device: int, max_pairs: int, max_bases: int):
+    With ``graphs`` the device steps of a batch (packing both sides and the
+    alignment) are one captured HIP graph, launched once per batch: every
+    batch is presented at the slot's capacity (the unused pair entries are
+    empty pairs, which the planner finishes at once, and the packed streams
+    are declared at their full capacity), so the same graph serves every
+    batch; only the request bytes, offsets and lengths are copied in before
+    the launch and the used results copied out after it."""
+
+    # longest sequence a captured batch declares (the bound its range guard checks)
+    GRAPH_MAX_LEN = 1 << 20
+
+    def __init__(self, device: int, max_pairs: int, max_bases: int, scoring: dict, w: int, Z: int,
+                 graphs: bool = True):
         self.lib = load_library()
         self.ctx = Context(device)
         self.stream = _torch().cuda.Stream(device=device)  # default priority
         self.device = device
+        self.scoring, self.w, self.Z = dict(scoring), int(w), int(Z)
+        self.graphs = bool(graphs)
+        self.graph = None
         self.max_pairs = self.max_bases = 0
         self._size(max_pairs, max_bases)
         self.reqs: Optional[List[_Request]] = None
@@ -63,30 +78,66 @@ class _Slot:
 
     def _size(self, max_pairs: int, max_bases: int):
         """(Re)allocate the staging buffers for batches of up to max_pairs
-        pairs and max_bases bases per side. Only an oversized request makes
-        a slot grow after start."""
+        pairs and max_bases bases per side (and drop the captured graph,
+        which names the old buffers). Only an oversized request makes a slot
+        grow after start."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
+        self.graph = None
         self.max_pairs, self.max_bases = P, B = int(max(max_pairs, 1)), int(max(max_bases, 1))
-        W = B // 16 + P + 1  # 2-bit words of one side: at most sum of ceil(len / 16)
+        self.W = W = B // 16 + P + 1  # 2-bit words of one side: at most sum of ceil(len / 16)
         pin = dict(pin_memory=True)
         self.h_ascii = [torch.empty(B, dtype=torch.uint8, **pin) for _ in range(2)]
-        self.h_off = [torch.empty(P, dtype=torch.int64, **pin) for _ in range(2)]
-        self.h_len = [torch.empty(P, dtype=torch.int32, **pin) for _ in range(2)]
+        # unused entries stay empty pairs (offset 0, length 0)
+        self.h_off = [torch.zeros(P, dtype=torch.int64, **pin) for _ in range(2)]
+        self.h_len = [torch.zeros(P, dtype=torch.int32, **pin) for _ in range(2)]
         self.h_out = torch.empty((P, 7), dtype=torch.int32, **pin)
-        self.d_ascii = [torch.empty(B, dtype=torch.uint8, device=dev) for _ in range(2)]
-        self.d_off = [torch.empty(P, dtype=torch.int64, device=dev) for _ in range(2)]
-        self.d_len = [torch.empty(P, dtype=torch.int32, device=dev) for _ in range(2)]
-        self.d_words = [torch.empty(W, dtype=torch.int32, device=dev) for _ in range(2)]
-        self.d_woff = [torch.empty(P, dtype=torch.int64, device=dev) for _ in range(2)]
-        self.d_nmask = [torch.empty((W + 1) // 2, dtype=torch.int32, device=dev) for _ in range(2)]
+        self.d_ascii = [torch.zeros(B, dtype=torch.uint8, device=dev) for _ in range(2)]
+        self.d_off = [torch.zeros(P, dtype=torch.int64, device=dev) for _ in range(2)]
+        self.d_len = [torch.zeros(P, dtype=torch.int32, device=dev) for _ in range(2)]
+        self.d_words = [torch.zeros(W, dtype=torch.int32, device=dev) for _ in range(2)]
+        self.d_woff = [torch.zeros(P, dtype=torch.int64, device=dev) for _ in range(2)]
+        self.d_nmask = [torch.zeros((W + 1) // 2, dtype=torch.int32, device=dev) for _ in range(2)]
         self.d_out = torch.empty((P, 7), dtype=torch.int32, device=dev)
+        torch.cuda.synchronize(self.device)
+
+    def _device_steps(self, st: int, n: int, nwords, max_len: int):
+        """Pack both sides and align n pairs, all enqueued on stream st."""
+        for side in range(2):
+            _check(self.lib.ga_pack(self.ctx.handle, self.d_ascii[side].data_ptr(), self.d_off[side].data_ptr(),
+                                    self.d_len[side].data_ptr(), n, nwords[side], self.d_words[side].data_ptr(),
+                                    self.d_woff[side].data_ptr(), self.d_nmask[side].data_ptr(), st), "ga_pack")
+        bt = Batch()
+        bt.n_pairs = n
+        bt.t_words_dev, bt.t_nwords = self.d_words[0].data_ptr(), nwords[0]
+        bt.q_words_dev, bt.q_nwords = self.d_words[1].data_ptr(), nwords[1]
+        bt.t_off_dev, bt.q_off_dev = self.d_woff[0].data_ptr(), self.d_woff[1].data_ptr()
+        bt.t_len_dev, bt.q_len_dev = self.d_len[0].data_ptr(), self.d_len[1].data_ptr()
+        bt.t_nmask_dev, bt.q_nmask_dev = self.d_nmask[0].data_ptr(), self.d_nmask[1].data_ptr()
+        bt.max_len = int(max_len)
+        sc = scoring_struct(self.scoring)
+        _check(self.lib.ga_align_batch(self.ctx.handle, ctypes.byref(bt), ctypes.byref(sc), self.w, self.Z,
+                                       self.d_out.data_ptr(), st), "ga_align_batch")
+
+    def _capture(self):
+        """Capture the capacity-shaped device steps (after one eager run on
+        the empty staging, which sizes the context's workspace)."""
+        torch = _torch()
+        shape = (self.max_pairs, [self.W, self.W], min(self.max_bases, self.GRAPH_MAX_LEN))
+        with torch.cuda.stream(self.stream):
+            self._device_steps(_stream_handle(self.stream), *shape)
+        self.stream.synchronize()
+        _check(self.lib.ga_context_check(self.ctx.handle, _stream_handle(self.stream)), "ga_context_check")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=self.stream):
+            self._device_steps(_stream_handle(torch.cuda.current_stream()), *shape)
+        self.graph = g
 
     @property
     def busy(self) -> bool:
         return self.reqs is not None
 
-    def launch(self, reqs: List[_Request], scoring: dict, w: int, Z: int):
+    def launch(self, reqs: List[_Request]):
         torch = _torch()
         n = len(reqs)
         lens = [np.array([len(r.target) for r in reqs], dtype=np.int32),
@@ -94,35 +145,31 @@ class _Slot:
         bases = max(int(lens[0].sum()), int(lens[1].sum()))
         if n > self.max_pairs or bases > self.max_bases:
             self._size(max(n, self.max_pairs), max(bases, self.max_bases))
-        nwords = [int(self.lib.ga_pack_words(l.ctypes.data, n)) for l in lens]
-        st = _stream_handle(self.stream)
+        max_len = int(max(lens[0].max(initial=0), lens[1].max(initial=0)))
+        use_graph = self.graphs and max_len <= self.GRAPH_MAX_LEN
+        if use_graph and self.graph is None:
+            self._capture()
+        P = self.max_pairs if use_graph else n
         with torch.cuda.stream(self.stream):
             for side in range(2):
                 seqs = b"".join(r.target if side == 0 else r.query for r in reqs)
                 off = np.zeros(n, dtype=np.int64)
                 off[1:] = np.cumsum(lens[side][:-1], dtype=np.int64)
                 self.h_ascii[side].numpy()[:len(seqs)] = np.frombuffer(seqs, dtype=np.uint8)
-                self.h_off[side].numpy()[:n] = off
-                self.h_len[side].numpy()[:n] = lens[side]
-                self.d_ascii[side][:max(len(seqs), 1)].copy_(self.h_ascii[side][:max(len(seqs), 1)],
-                                                            non_blocking=True)
-                self.d_off[side][:n].copy_(self.h_off[side][:n], non_blocking=True)
-                self.d_len[side][:n].copy_(self.h_len[side][:n], non_blocking=True)
-                _check(self.lib.ga_pack(self.ctx.handle, self.d_ascii[side].data_ptr(), self.d_off[side].data_ptr(),
-                                        self.d_len[side].data_ptr(), n, nwords[side],
-                                        self.d_words[side].data_ptr(), self.d_woff[side].data_ptr(),
-                                        self.d_nmask[side].data_ptr(), st), "ga_pack")
-            bt = Batch()
-            bt.n_pairs = n
-            bt.t_words_dev, bt.t_nwords = self.d_words[0].data_ptr(), nwords[0]
-            bt.q_words_dev, bt.q_nwords = self.d_words[1].data_ptr(), nwords[1]
-            bt.t_off_dev, bt.q_off_dev = self.d_woff[0].data_ptr(), self.d_woff[1].data_ptr()
-            bt.t_len_dev, bt.q_len_dev = self.d_len[0].data_ptr(), self.d_len[1].data_ptr()
-            bt.t_nmask_dev, bt.q_nmask_dev = self.d_nmask[0].data_ptr(), self.d_nmask[1].data_ptr()
-            bt.max_len = int(max(lens[0].max(initial=0), lens[1].max(initial=0)))
-            sc = scoring_struct(scoring)
-            _check(self.lib.ga_align_batch(self.ctx.handle, ctypes.byref(bt), ctypes.byref(sc), int(w), int(Z),
-                                           self.d_out.data_ptr(), st), "ga_align_batch")
+                h_off, h_len = self.h_off[side].numpy(), self.h_len[side].numpy()
+                h_off[:n] = off
+                h_len[:n] = lens[side]
+                h_off[n:P] = 0
+                h_len[n:P] = 0
+                nb = max(len(seqs), 1)
+                self.d_ascii[side][:nb].copy_(self.h_ascii[side][:nb], non_blocking=True)
+                self.d_off[side][:P].copy_(self.h_off[side][:P], non_blocking=True)
+                self.d_len[side][:P].copy_(self.h_len[side][:P], non_blocking=True)
+            if use_graph:
+                self.graph.replay()
+            else:
+                nwords = [int(self.lib.ga_pack_words(l.ctypes.data, n)) for l in lens]
+                self._device_steps(_stream_handle(self.stream), n, nwords, max_len)
             self.h_out[:n].copy_(self.d_out[:n], non_blocking=True)
             self.event = torch.cuda.Event()
             self.event.record(self.stream)
@@ -160,11 +207,12 @@ class Server:
 
     def __init__(self, scoring: dict, w: int, Z: int, device: int = 0, slots: int = 2,
                  long_slots: int = 1, max_batch_pairs: int = 256, max_batch_bases: int = 1_000_000,
-                 long_bases: int = 8000, long_batch_pairs: int = 4096, long_batch_bases: int = 16_000_000):
+                 long_bases: int = 8000, long_batch_pairs: int = 4096, long_batch_bases: int = 16_000_000,
+                 graphs: bool = True):
         self.scoring, self.w, self.Z = dict(scoring), int(w), int(Z)
         self.pairs = [int(max_batch_pairs), int(long_batch_pairs)]
         self.limits = [int(max_batch_bases), int(long_batch_bases)]
-        self.lanes = [[_Slot(device, self.pairs[k], self.limits[k]) for _ in range(n)]
+        self.lanes = [[_Slot(device, self.pairs[k], self.limits[k], scoring, w, Z, graphs) for _ in range(n)]
                       for k, n in enumerate((slots, long_slots))]
         self.long_bases = int(long_bases)
         self.pending = [collections.deque(), collections.deque()]
@@ -187,7 +235,7 @@ class Server:
             seq = rng.choice(acgt, L).tobytes()
             reqs = [_Request(-1, seq, b"A", 0.0) for _ in range(P)]
             for slot in lane:
-                slot.launch(reqs, self.scoring, self.w, self.Z)
+                slot.launch(reqs)
         torch.cuda.synchronize(device)
         for lane in self.lanes:
             for slot in lane:
@@ -226,7 +274,7 @@ class Server:
                 if not q:
                     break
                 if not slot.busy:
-                    slot.launch(self._take_batch(q, P, limit), self.scoring, self.w, self.Z)
+                    slot.launch(self._take_batch(q, P, limit))
                     self.batches += 1
         return done
 
@@ -305,6 +353,7 @@ def main(argv=None):
     ap.add_argument("--max-batch-bases", type=int, default=1_000_000)
     ap.add_argument("--long-batch-pairs", type=int, default=4096)
     ap.add_argument("--long-batch-bases", type=int, default=16_000_000)
+    ap.add_argument("--no-graphs", action="store_true", help="enqueue each batch's steps eagerly")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args(argv)
     torch = _torch()
@@ -312,7 +361,7 @@ def main(argv=None):
     batch = seqgen.make_config(5, n_pairs=args.requests, seed=args.seed)
     kw = dict(slots=args.slots, long_slots=args.long_slots, max_batch_pairs=args.max_batch_pairs,
               max_batch_bases=args.max_batch_bases, long_batch_pairs=args.long_batch_pairs,
-              long_batch_bases=args.long_batch_bases)
+              long_batch_bases=args.long_batch_bases, graphs=not args.no_graphs)
     res_off, dt_off = offline(batch)
     cells = int(count_cells(batch.t_len, batch.q_len, batch.w, res_off).sum())
     sys.stderr.write(f"[serve] offline: {batch.n_pairs} requests as one batch in {dt_off * 1e3:.1f} ms "
@@ -342,7 +391,7 @@ def main(argv=None):
             "p99_long_ms": round(float(np.percentile(lat[long_], 99)) * 1e3, 3) if long_.any() else None,
             "gcups": round(cells / wall / 1e9, 3), "offline_gcups": round(cells / dt_off / 1e9, 3),
             "saturated_gcups": round(cells / wall_sat / 1e9, 3),
-            "batches": nb, "wall_s": round(wall, 3), "same_as_offline": same,
+            "batches": nb, "wall_s": round(wall, 3), "same_as_offline": same, "graphs": not args.no_graphs,
             "workload": "seqgen workload 5: 95% pairs of 100-1000 bp (5% errors), 5% of 10-25 kb "
                         "(1% errors + indels), w=500, Z=400, Poisson arrivals",
         }

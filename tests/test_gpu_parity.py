@@ -522,3 +522,44 @@ def test_cli_fasta(tmp_path):
     assert_same(got, want, None, "cli")
     meta = json.loads((out / "time.json").read_text())
     assert meta["pairs"] == b.n_pairs and meta["kernel_ms"] > 0
+
+
+def test_graph_replays_match_eager():
+    """A serving slot replays one captured HIP graph (packing and alignment at
+    the slot's capacity) for batches of different sizes; every replay, with
+    eager work and synchronisation between replays, equals the eager call
+    on the same pairs and the oracle."""
+    import time
+
+    import torch
+
+    from paper_2403_06478_amd import serve
+    rng = np.random.default_rng(53)
+    sc = dict(seqgen.SCORING)
+    slot = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=True)
+    eager = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=False)
+    for k, n in enumerate([16, 1, 9, 16, 5]):
+        b = seqgen.random_pairs(rng, n, 0, 700, err=0.1, n_rate=0.01, related=0.8, w=200, zdrop=150)
+        reqs = [serve._Request(i, b.target(i), b.query(i), 0.0) for i in range(n)]
+        _say(f"graph replay {k}: {n} pairs")
+        for s in (slot, eager):
+            s.launch(reqs)
+        got = {}
+        for name, s in (("graph", slot), ("eager", eager)):
+            for _ in range(20000):
+                r = s.poll()
+                if r is not None:
+                    got[name] = r[1]
+                    break
+                time.sleep(0.0005)
+        assert slot.graph is not None and eager.graph is None
+        assert np.array_equal(got["graph"], got["eager"]), k
+        assert np.array_equal(got["graph"], gpu_align(b)), k
+        want, _ = oracle_align(b)
+        assert_same(got["graph"], want, b, f"graph replay {k}")
+        # unrelated eager work and a full synchronisation between replays
+        x = torch.arange(1 << 20, device="cuda", dtype=torch.int32)
+        assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
+        torch.cuda.synchronize()
+    slot.ctx.close()
+    eager.ctx.close()
