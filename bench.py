@@ -105,6 +105,8 @@ def main():
                     help="ont (the headline batch, default), longread or mixed")
     ap.add_argument("--schedule", choices=["persistent", "bucketed"], default="persistent",
                     help="persistent (default) or the plain per-length-bucket launches, for comparison")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default class order instead of the measured one")
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs (profiling runs only)")
     ap.add_argument("--cpu-sample", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -132,6 +134,14 @@ def main():
     batch = seqgen.make_config(wid, n_pairs=args.pairs)
     ctx = ga.Context(0)
     ctx.set_schedule(args.schedule)
+    class_cost = None
+    if not args.no_autotune:
+        # set-up, outside the timed steps: measure each kernel class, then
+        # every pair takes the cheapest class that runs it
+        class_cost = ctx.autotune()
+        order = sorted(range(len(ga.CLASSES)), key=lambda c: class_cost[c])
+        log("autotuned class costs (ns per pair and anti-diagonal): " +
+            ", ".join(f"{ga.class_name(c)} {class_cost[c]:.3f}" for c in order))
     packed = ga.pack_batch(ctx, batch)
     out = torch.empty((batch.n_pairs, 7), dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
@@ -213,6 +223,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": wdesc, "schedule": args.schedule,
+                   "class_choice": "autotuned" if class_cost is not None else "default order",
                    "pairs": batch.n_pairs, "w": batch.w, "Z": batch.zdrop,
                    "cells": total_cells, "zdropped": int(res[:, 6].sum())},
         "pairs_per_s": round(pairs_per_s, 1),

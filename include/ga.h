@@ -162,6 +162,25 @@ int ga_context_set_schedule(ga_context_t *ctx, int schedule);
  * GA_EINVAL for an empty mask or bits above class 10. */
 int ga_context_set_classes(ga_context_t *ctx, uint32_t mask);
 
+/* Autotuner (the context's autotune table): runs a synthetic probe batch
+ * through every kernel class on this context's device -- random pairs with
+ * about one substitution in 16, in the shape the cheapest-first rule gives
+ * each class (the band filling 7/8 of its slots; short-by-long pairs for the
+ * sliding classes), enough pairs for two rounds of resident workgroups --
+ * and times each class's launch. ns_per_step[c] (c < n, n <= 11) receives
+ * the measured cost of class c in nanoseconds per pair and anti-diagonal at
+ * full occupancy. Later ga_align_batch calls on this context then try the
+ * classes cheapest first: each pair takes the cheapest allowed class that
+ * runs it (results do not depend on the class). This is where the shape
+ * choices of Sections 5.5 and 5.7 (slice width, subwarp size) are made by
+ * measurement. Allocates temporary device memory and synchronises
+ * `stream`; on an error the default order is in force. */
+int ga_context_autotune(ga_context_t *ctx, float *ns_per_step, int n, void *stream);
+
+/* The class ga_align_batch on this context picks for a pair of lengths
+ * n, m at band w (its class mask and autotuned order); -1 if none. */
+int ga_context_pair_class(const ga_context_t *ctx, int32_t n, int32_t m, int32_t w);
+
 /* Stage timing for benchmarking: while enabled, ga_align_batch records HIP
  * events on its stream around its stages. */
 int ga_context_set_timing(ga_context_t *ctx, int enable);

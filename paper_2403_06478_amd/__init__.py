@@ -32,7 +32,7 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_pack_words", "ga_pack", "ga_align_batch", "ga_count_cells",
                "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
                "ga_calibrate_valu", "ga_context_set_schedule", "ga_context_set_classes",
-               "ga_pair_class_in")
+               "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
@@ -122,6 +122,10 @@ def load_library() -> ctypes.CDLL:
     lib.ga_pair_class_in.restype = ctypes.c_int
     lib.ga_context_set_classes.argtypes = [vp, ctypes.c_uint32]
     lib.ga_context_set_classes.restype = ctypes.c_int
+    lib.ga_context_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int, vp]
+    lib.ga_context_autotune.restype = ctypes.c_int
+    lib.ga_context_pair_class.argtypes = [vp, i32, i32, i32]
+    lib.ga_context_pair_class.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -191,6 +195,18 @@ class Context:
         ``CLASSES``); None allows all."""
         mask = (1 << len(CLASSES)) - 1 if classes is None else sum(1 << int(c) for c in set(classes))
         _check(load_library().ga_context_set_classes(self._h, mask), "ga_context_set_classes")
+
+    def autotune(self, stream=None):
+        """Measure every kernel class on this device and try them cheapest
+        first from now on; returns the costs (ns per pair and anti-diagonal)."""
+        n = len(CLASSES)
+        ns = (ctypes.c_float * n)()
+        _check(load_library().ga_context_autotune(self._h, ns, n, _stream_handle(stream)), "ga_context_autotune")
+        return [float(x) for x in ns]
+
+    def pair_class(self, n: int, m: int, w: int) -> int:
+        """The class ga_align_batch on this context picks for the pair."""
+        return int(load_library().ga_context_pair_class(self._h, int(n), int(m), int(w)))
 
     def calibrate_valu(self, stream=None) -> float:
         """Measured int32 VALU lane-ops per second of this device."""

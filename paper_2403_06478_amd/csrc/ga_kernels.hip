@@ -76,8 +76,16 @@ constexpr uint32_t ALL_CLASSES = (1u << NCLASS) - 1;
 // is then taken only in the shape the cheapest-first rule gives it: a
 // sliding class only for a band wider than its window, a class of NW waves
 // only for a band that reaches its last wave.
+// The classes in the order they are tried: cheapest first, four bits per
+// class from the lowest nibble. The default is by slots per lane (4, 8,
+// sliding 8, 16, sliding 16, 24, 32), then the multi-wave classes; an
+// autotuned context replaces it with its measured order.
+constexpr uint64_t DEFAULT_ORDER = 0x0ull | (1ull << 4) | (5ull << 8) | (2ull << 12) | (6ull << 16) |
+                                   (3ull << 20) | (4ull << 24) | (7ull << 28) | (8ull << 32) |
+                                   (9ull << 36) | (10ull << 40);
+
 __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *slide,
-                                         uint32_t mask = ALL_CLASSES) {
+                                         uint32_t mask = ALL_CLASSES, uint64_t order = DEFAULT_ORDER) {
     int64_t a0, a1;
     if (w >= 0) {
         a0 = -w > -m ? -w : -m;
@@ -89,10 +97,8 @@ __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *s
     const int64_t D = a1 - a0 + 1;
     const int64_t span = 2 * (n < m ? n : m) + 11;
     *slide = 0;
-    // cheapest first: fewer slots per lane, then fewer waves
-    const int order[NCLASS] = {0, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10};
     for (int k = 0; k < NCLASS; ++k) {
-        const int c = order[k];
+        const int c = (int)((order >> (4 * k)) & 0xFull);
         if (!((mask >> c) & 1u)) continue;
         if (!class_slides(c)) {
             if (D <= class_cap(c) && D > WAVE * class_k(c) * (class_nw(c) - 1)) return c;
@@ -1130,6 +1136,7 @@ struct PlanArgs {
     int32_t bucketed;  // schedule: 0 persistent, 1 bucketed
     int32_t ordered;   // persistent: order each class longest first
     uint32_t mask;     // kernel classes allowed
+    uint64_t order;    // the order classes are tried in (class_for)
     int32_t *counters;
     int32_t *hist;    // [PLAN_BINS] pairs per (group, cost bucket)
     int32_t *cursor;  // [PLAN_BINS] next list position per (group, cost bucket)
@@ -1164,7 +1171,7 @@ __global__ void ga_plan_classify(PlanArgs A) {
             if (bucket_class(group, A.w, A.mask) < 0) group = -1;
         } else {
             int slide;
-            group = class_for(n, m, A.w, &slide, A.mask);
+            group = class_for(n, m, A.w, &slide, A.mask, A.order);
             bucket = A.ordered ? min((n + m) >> PLAN_SHIFT, PLAN_BUCKETS - 1) : 0;
         }
         if (group < 0) {
@@ -1298,6 +1305,43 @@ __global__ void ga_pack_kernel(const uint8_t *ascii, const int64_t *off, const i
     }
 }
 
+// Probe pairs for the autotuner: pair p has a target of n random bases and
+// a query of m bases copying the target's first m with about one
+// substitution in 16 (no N). Bases come from an integer hash of the pair,
+// word and base indices (the lowbias32 mixer of C. Wellons).
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void ga_probe_fill(int64_t n_pairs, int32_t n, int32_t m, uint32_t *t_words, uint32_t *q_words,
+                              int64_t *t_off, int64_t *q_off, int32_t *t_len, int32_t *q_len) {
+    const int64_t tw = ((int64_t)n + 15) / 16, qw = ((int64_t)m + 15) / 16;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n_pairs * tw) return;
+    const int64_t p = idx / tw, k = idx % tw;
+    const uint32_t v = mix32((uint32_t)p * 0x9e3779b9u ^ mix32((uint32_t)k + 0x5bd1e995u));
+    t_words[idx] = v;
+    if (k < qw) {
+        uint32_t x = 0;
+        for (int b = 0; b < 16; ++b) {
+            const uint32_t h = mix32(v ^ ((uint32_t)b * 0x27d4eb2fu) ^ (uint32_t)k);
+            if ((h & 15u) == 0) x |= (1u + (h >> 4) % 3u) << (2 * b);
+        }
+        q_words[p * qw + k] = v ^ x;
+    }
+    if (k == 0) {
+        t_off[p] = p * tw;
+        q_off[p] = p * qw;
+        t_len[p] = n;
+        q_len[p] = m;
+    }
+}
+
 }  // namespace
 
 // --------------------------------------------------------------- host side
@@ -1315,6 +1359,8 @@ struct ga_context {
     int timed_last;    // the last ga_align_batch recorded them
     int schedule;      // GA_SCHED_*
     uint32_t class_mask;  // kernel classes the planner may use
+    uint64_t class_order; // the order the planner tries them in (autotune table)
+    float class_cost[NCLASS];  // measured ns per pair and anti-diagonal (0: not tuned)
     int n_launch_last;              // launches of the last timed call
     int launch_class[NGROUP];       // their kernel classes
     int32_t *h_counts;              // pinned host copy of the group sizes (bucketed schedule)
@@ -1416,6 +1462,7 @@ int ga_context_create(ga_context_t **out, int device) {
     if (!ctx) return GA_ENOMEM;
     ctx->device = device;
     ctx->class_mask = ALL_CLASSES;
+    ctx->class_order = DEFAULT_ORDER;
     if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         ctx->num_cu = 256;
     // persistent grids: as many workgroups as the registers let reside
@@ -1510,6 +1557,112 @@ int ga_context_set_schedule(ga_context_t *ctx, int schedule) {
 int ga_context_set_classes(ga_context_t *ctx, uint32_t mask) {
     if (!ctx || mask == 0 || (mask & ~ALL_CLASSES) != 0) return GA_EINVAL;
     ctx->class_mask = mask;
+    return GA_OK;
+}
+
+int ga_context_pair_class(const ga_context_t *ctx, int32_t n, int32_t m, int32_t w) {
+    if (!ctx || n <= 0 || m <= 0) return -1;
+    int slide;
+    return class_for(n, m, w, &slide, ctx->class_mask, ctx->class_order);
+}
+
+// Anti-diagonals a full sweep of an (n, m) pair at band w visits (the last
+// one with an interior cell, plus one), as the kernels' geometry has it.
+static int64_t sweep_steps(int64_t n, int64_t m, int64_t w) {
+    const int64_t a0 = w >= 0 ? (-w > -m ? -w : -m) : -m;
+    const int64_t a1 = w >= 0 ? (w < n ? w : n) : n;
+    const int64_t dlo = a0 > 1 - m ? a0 : 1 - m;
+    const int64_t dhi = a1 < n - 1 ? a1 : n - 1;
+    int64_t dc = n - m;
+    if (dc < dlo) dc = dlo;
+    if (dc > dhi) dc = dhi;
+    const int64_t x = 2 * n - 2 - dc, y = 2 * m - 2 + dc;
+    return (x < y ? x : y) + 1;
+}
+
+int ga_context_autotune(ga_context_t *ctx, float *ns_per_step, int n_out, void *stream) {
+    if (!ctx || n_out < 0 || (n_out > 0 && !ns_per_step)) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t mask0 = ctx->class_mask;
+    const int sched0 = ctx->schedule, timing0 = ctx->timing;
+    ctx->schedule = GA_SCHED_PERSISTENT;
+    ctx->class_order = DEFAULT_ORDER;
+    int rc = ga_context_set_timing(ctx, 1);
+    const ga_scoring_t sc{2, 4, 4, 2, 24, 1, 1};
+    float cost[NCLASS];
+    for (int c = 0; c < NCLASS && rc == GA_OK; ++c) {
+        // a probe each class runs in the shape the cheapest-first rule gives it
+        const int K = class_k(c), cap = class_cap(c);
+        int n, m, w;
+        if (class_slides(c)) {
+            m = (cap - 11 - K) / 2 - 4;  // the short side's span fits the window
+            n = 8 * cap;
+            w = 2 * cap;                 // the band does not
+        } else {
+            const int lo = WAVE * K * (class_nw(c) - 1);
+            const int D = lo + (cap - lo) * 7 / 8;
+            w = (D - 1) / 2;
+            n = m = 2 * w + 1024;
+        }
+        const int64_t pairs = 2 * (int64_t)ctx->blocks_per_cu[c] * ctx->num_cu;
+        const int64_t tw = ((int64_t)n + 15) / 16, qw = ((int64_t)m + 15) / 16;
+        char *buf = nullptr;
+        const size_t o_q = align_up(sizeof(uint32_t) * pairs * tw, 256);
+        const size_t o_to = o_q + align_up(sizeof(uint32_t) * pairs * qw, 256);
+        const size_t o_qo = o_to + align_up(sizeof(int64_t) * pairs, 256);
+        const size_t o_tl = o_qo + align_up(sizeof(int64_t) * pairs, 256);
+        const size_t o_ql = o_tl + align_up(sizeof(int32_t) * pairs, 256);
+        const size_t o_out = o_ql + align_up(sizeof(int32_t) * pairs, 256);
+        const size_t total = o_out + sizeof(ga_result_t) * pairs;
+        if (hipMalloc(&buf, total) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = GA_ENOMEM;
+            break;
+        }
+        ga_batch_t bt{};
+        bt.n_pairs = pairs;
+        bt.t_words_dev = (const uint32_t *)buf;
+        bt.t_nwords = pairs * tw;
+        bt.q_words_dev = (const uint32_t *)(buf + o_q);
+        bt.q_nwords = pairs * qw;
+        bt.t_off_dev = (const int64_t *)(buf + o_to);
+        bt.q_off_dev = (const int64_t *)(buf + o_qo);
+        bt.t_len_dev = (const int32_t *)(buf + o_tl);
+        bt.q_len_dev = (const int32_t *)(buf + o_ql);
+        bt.max_len = n > m ? n : m;
+        const int64_t nthr = pairs * tw;
+        hipLaunchKernelGGL(ga_probe_fill, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, pairs, n, m,
+                           (uint32_t *)buf, (uint32_t *)(buf + o_q), (int64_t *)(buf + o_to),
+                           (int64_t *)(buf + o_qo), (int32_t *)(buf + o_tl), (int32_t *)(buf + o_ql));
+        ctx->class_mask = 1u << c;
+        float ms[1 + NCLASS] = {};
+        for (int rep = 0; rep < 2 && rc == GA_OK; ++rep)  // the first run warms up
+            rc = ga_align_batch(ctx, &bt, &sc, w, -1, (ga_result_t *)(buf + o_out), s);
+        if (rc == GA_OK) rc = ga_context_timing(ctx, ms, 1 + NCLASS);
+        if (rc == GA_OK) rc = ga_context_check(ctx, s);
+        (void)hipFree(buf);
+        cost[c] = (float)(ms[1 + c] * 1e6 / ((double)pairs * (double)sweep_steps(n, m, w)));
+    }
+    ctx->class_mask = mask0;
+    ctx->schedule = sched0;
+    const int rc2 = ga_context_set_timing(ctx, timing0);
+    if (rc == GA_OK) rc = rc2;
+    if (rc != GA_OK) return rc;
+    // cheapest first (insertion sort; ties keep the default order)
+    int ord[NCLASS];
+    for (int k = 0; k < NCLASS; ++k) ord[k] = (int)((DEFAULT_ORDER >> (4 * k)) & 0xFull);
+    for (int k = 1; k < NCLASS; ++k)
+        for (int j = k; j > 0 && cost[ord[j]] < cost[ord[j - 1]]; --j) {
+            const int t = ord[j];
+            ord[j] = ord[j - 1];
+            ord[j - 1] = t;
+        }
+    uint64_t order = 0;
+    for (int k = 0; k < NCLASS; ++k) order |= (uint64_t)ord[k] << (4 * k);
+    ctx->class_order = order;
+    for (int c = 0; c < NCLASS; ++c) ctx->class_cost[c] = cost[c];
+    for (int c = 0; c < n_out && c < NCLASS; ++c) ns_per_step[c] = cost[c];
     return GA_OK;
 }
 
@@ -1683,6 +1836,7 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     pa.bucketed = ctx->schedule == GA_SCHED_BUCKETED ? 1 : 0;
     pa.ordered = ctx->schedule == GA_SCHED_PERSISTENT ? 1 : 0;
     pa.mask = ctx->class_mask;
+    pa.order = ctx->class_order;
     pa.counters = counters;
     pa.hist = (int32_t *)(ws + off_hist);
     pa.cursor = (int32_t *)(ws + off_cursor);

@@ -563,3 +563,35 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
     slot.ctx.close()
     eager.ctx.close()
+
+
+def test_autotune_order_and_results():
+    """The autotuner measures every class; afterwards each pair takes the
+    cheapest (by the measured costs) allowed class that runs it, and the
+    results stay those of the default order and the oracle."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    ctx = ga.Context(0)
+    cost = ctx.autotune()
+    _say("autotune: " + ", ".join(f"{ga.class_name(c)}={cost[c]:.3f}" for c in range(len(cost))))
+    assert len(cost) == len(ga.CLASSES) and all(np.isfinite(cost)) and min(cost) > 0
+    rng = np.random.default_rng(61)
+    every = range(len(ga.CLASSES))
+    for _ in range(2000):
+        n, m = (int(x) for x in rng.integers(1, 9000, 2))
+        w = int(rng.choice([-1, 50, 300, 751, 1000, 1500, 2500, 3500]))
+        holders = [c for c in every if ga.ga_pair_class_in(n, m, w, [c]) == c]
+        got = ctx.pair_class(n, m, w)
+        if not holders:
+            assert got == -1
+            continue
+        assert got in holders and cost[got] == min(cost[c] for c in holders), (n, m, w, got, holders)
+    b = seqgen.make_config(1)
+    packed = ga.pack_batch(ctx, b)
+    out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+    torch.cuda.synchronize()
+    ctx.check()
+    want, _ = oracle_align(b)
+    assert_same(out.cpu().numpy(), want, b, "autotuned cfg1")
+    ctx.close()
