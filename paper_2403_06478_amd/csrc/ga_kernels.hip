@@ -476,55 +476,49 @@ __device__ __forceinline__ int lane_max(const PairState<K> &st, const Geo &g, in
 }
 
 // One wave per pair: the decisions for anti-diagonal r (class C) from its
-// lane maxima lm and wave maximum MA: local maximum (Eq. 6), global maximum
-// (Eq. 7) and the z-drop test (Eq. 5). They run one step late, after the
-// update of anti-diagonal r+1, which leaves class C untouched. Returns 0 to
-// go on, 1 when the sweep ends at its last anti-diagonal, 2 on a z-drop.
+// lane maxima lm and wave maximum MA (frame value of the local maximum M of
+// Eq. 6). They run one step late, after the update of anti-diagonal r+1,
+// which leaves class C untouched. The common case takes only take_max (M
+// above G: the global maximum of Eq. 7 moves, the class is parked so its
+// cell can be found later); the end of the sweep and z-drop candidates
+// (Eq. 5) go to finish_diag, which returns 0 to go on, 1 when the sweep
+// ends at its last anti-diagonal and 2 on a z-drop.
 template <int K, int C>
-__device__ __forceinline__ int decide(const PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
-                                       int r, int lane, int lm, int MA, int vlo, int vhi, bool masked,
-                                       PairLds<K, 1> &S) {
-    const int M = MA + P.q1 - P.e1 * r;  // back to the true score
+__device__ __forceinline__ void take_max(const PairState<K> &st, const Geo &g, Track &tr, int r, int lane,
+                                         int MA, int M, PairLds<K, 1> &S) {
+    park_class<K, C, 1>(st, S, lane);
+    tr.G = M;
+    tr.g_r = r;
+    tr.g_base = g.a0w;
+    tr.g_cls = C;
+    tr.g_ma = MA;
+    tr.g_open = true;
+    tr.g_set = true;
+}
+
+template <int K, int C>
+__device__ __forceinline__ int finish_diag(const PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
+                                           int r, int lane, int lm, int MA, int M, bool up, int vlo, int vhi,
+                                           bool masked, PairLds<K, 1> &S) {
     const bool last = r >= g.r_last;
-    if (M > tr.G) {
-        park_class<K, C, 1>(st, S, lane);
-        tr.G = M;
-        tr.g_r = r;
-        tr.g_base = g.a0w;
-        tr.g_cls = C;
-        tr.g_ma = MA;
-        tr.g_open = true;
-        tr.g_set = true;
-        if (last) {
-            if (!masked) diag_window(g, r, vlo, vhi);
-            int mi, mj;
-            locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
-            tr.endS = M;
-            tr.endI = mi;
-            tr.endJ = mj;
+    if (!masked) diag_window(g, r, vlo, vhi);
+    int mi, mj;
+    locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
+    tr.endS = M;
+    tr.endI = mi;
+    tr.endJ = mj;
+    if (!up && P.Z >= 0 && tr.G - M > P.Z) {
+        if (tr.g_open) {
+            int gi, gj;
+            park_cell<K, 1>(tr, g, S, lane, gi, gj);
+            tr.gi = gi;
+            tr.gj = gj;
+            tr.g_open = false;
         }
-        return last ? 1 : 0;
-    }
-    if (__builtin_expect((P.Z >= 0 && tr.G - M > P.Z) || last, 0)) {
-        if (!masked) diag_window(g, r, vlo, vhi);
-        int mi, mj;
-        locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
-        tr.endS = M;
-        tr.endI = mi;
-        tr.endJ = mj;
-        if (P.Z >= 0 && tr.G - M > P.Z) {
-            if (tr.g_open) {
-                int gi, gj;
-                park_cell<K, 1>(tr, g, S, lane, gi, gj);
-                tr.gi = gi;
-                tr.gj = gj;
-                tr.g_open = false;
-            }
-            if (mi > tr.gi && mj > tr.gj) {
-                int dd = (mi - tr.gi) - (mj - tr.gj);
-                dd = dd < 0 ? -dd : dd;
-                if (tr.G - M > P.Z + P.e2 * dd) return 2;
-            }
+        if (mi > tr.gi && mj > tr.gj) {
+            int dd = (mi - tr.gi) - (mj - tr.gj);
+            dd = dd < 0 ? -dd : dd;
+            if (tr.G - M > P.Z + P.e2 * dd) return 2;
         }
     }
     return last ? 1 : 0;
@@ -727,10 +721,17 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
                     MA = wave_max(lm);                                                     \
                 }                                                                          \
                 if (MA > LIVE_MIN) {  /* the anti-diagonal has an interior cell */         \
-                    const int rc = decide<K, CP>(st, P, g, tr, rp, lane, lm, MA, vlo, vhi, mp, S); \
-                    if (rc) {                                                              \
-                        tr.zd = rc >> 1;                                                   \
-                        return true;                                                       \
+                    const int M = MA + P.q1 - P.e1 * rp;  /* back to the true score */     \
+                    const bool up = M > tr.G;                                              \
+                    if (up) take_max<K, CP>(st, g, tr, rp, lane, MA, M, S);                \
+                    if (__builtin_expect(rp >= g.r_last ||                                 \
+                                         (!up && P.Z >= 0 && tr.G - M > P.Z), 0)) {       \
+                        const int rc = finish_diag<K, CP>(st, P, g, tr, rp, lane, lm, MA, M, up, \
+                                                          vlo, vhi, mp, S);                \
+                        if (rc) {                                                          \
+                            tr.zd = rc >> 1;                                               \
+                            return true;                                                   \
+                        }                                                                  \
                     }                                                                      \
                 }                                                                          \
             }                                                                              \
