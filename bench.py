@@ -181,15 +181,20 @@ def main():
     res = out.cpu().numpy()
     t_len, q_len = batch.t_len, batch.q_len
     cells = ga.count_cells(t_len, q_len, batch.w, res)
-    cls = np.array([ga.ga_pair_class(int(n), int(m), batch.w) for n, m in zip(t_len, q_len)])
+    # the class each pair ran in (this context's autotuned order)
+    cls = np.array([ctx.pair_class(int(n), int(m), batch.w) for n, m in zip(t_len, q_len)])
     total_cells = int(cells.sum())
     gcups = total_cells / (ms_per_step / 1e3) / 1e9
     pairs_per_s = batch.n_pairs / (ms_per_step / 1e3)
 
     stage = np.array(stage_ms)  # [steps, 1 + classes]
     mean_ms = stage.mean(axis=0)
-    dom = int(np.argmax(mean_ms[1:]))
-    dom_cells = int(cells[cls == dom].sum())
+    # the dominant kernel is the class that computed the most cells (the
+    # classes' launches overlap on several streams, so an empty launch can
+    # span another class's run while it waits for the GPU)
+    per_class = np.array([int(cells[cls == c].sum()) for c in range(len(ga.CLASSES))])
+    dom = int(np.argmax(per_class))
+    dom_cells = int(per_class[dom])
     achieved = OPS_PER_CELL * dom_cells / (mean_ms[1 + dom] / 1e3) / 1e12
     traffic = read_traffic(ga.class_name(dom))
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_TOPS, 2),

@@ -149,6 +149,16 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_
  * GA_EINVAL for an unknown schedule. */
 int ga_context_set_schedule(ga_context_t *ctx, int schedule);
 
+/* Streams the persistent launches of one ga_align_batch call spread over
+ * (1..3; default 3): the caller's stream plus up to two streams the context
+ * owns, forked from and joined back into the caller's stream, so the call
+ * stays ordered on `stream` while the launches of different kernel classes
+ * overlap on the device (the tail of one class -- its last, longest pairs
+ * -- runs beside the next). 1 keeps every launch on `stream` (e.g. where
+ * many contexts share the GPU's few hardware queues). GA_EINVAL outside
+ * 1..3. */
+int ga_context_set_lanes(ga_context_t *ctx, int lanes);
+
 /* Restrict the kernel classes (bit c = class c, see ga_context_timing) that
  * later ga_align_batch calls on this context may use; the default is all
  * eleven. Each pair takes the cheapest allowed class that runs it in the

@@ -32,7 +32,7 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_pack_words", "ga_pack", "ga_align_batch", "ga_count_cells",
                "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
                "ga_calibrate_valu", "ga_context_set_schedule", "ga_context_set_classes",
-               "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class")
+               "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class", "ga_context_set_lanes")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
@@ -122,6 +122,8 @@ def load_library() -> ctypes.CDLL:
     lib.ga_pair_class_in.restype = ctypes.c_int
     lib.ga_context_set_classes.argtypes = [vp, ctypes.c_uint32]
     lib.ga_context_set_classes.restype = ctypes.c_int
+    lib.ga_context_set_lanes.argtypes = [vp, ctypes.c_int]
+    lib.ga_context_set_lanes.restype = ctypes.c_int
     lib.ga_context_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int, vp]
     lib.ga_context_autotune.restype = ctypes.c_int
     lib.ga_context_pair_class.argtypes = [vp, i32, i32, i32]
@@ -189,6 +191,10 @@ class Context:
         longest-first order) or 'bucketed' (the plain per-length-bucket
         baseline)."""
         _check(load_library().ga_context_set_schedule(self._h, SCHEDULES[schedule]), "ga_context_set_schedule")
+
+    def set_lanes(self, lanes: int):
+        """Streams (1..3) the persistent launches of one call overlap on."""
+        _check(load_library().ga_context_set_lanes(self._h, int(lanes)), "ga_context_set_lanes")
 
     def set_classes(self, classes=None):
         """Restrict the kernel classes later calls may use (indices into

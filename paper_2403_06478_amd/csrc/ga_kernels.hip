@@ -1347,7 +1347,15 @@ __global__ void ga_probe_fill(int64_t n_pairs, int32_t n, int32_t m, uint32_t *t
 
 // --------------------------------------------------------------- host side
 
-constexpr int NEVENTS = 2 + NGROUP;
+// Stage events of a timed call: start, end of planning, then a start and
+// an end per launch (recorded on the stream the launch runs on).
+constexpr int NEVENTS = 2 + 2 * NGROUP;
+// The persistent launches run on up to three streams at once (the caller's
+// and two of the context's), joined back into the caller's stream; the
+// lane of each class is fixed so the heavy classes of a mixed batch (K=24,
+// sliding K=8, K=4, K=16) land on different streams.
+constexpr int MAX_LANES = 3;
+constexpr int LANE_OF[NCLASS] = {0, 2, 1, 0, 1, 1, 2, 1, 0, 2, 0};
 
 struct ga_context {
     int device;
@@ -1363,6 +1371,9 @@ struct ga_context {
     uint64_t class_order; // the order the planner tries them in (autotune table)
     float class_cost[NCLASS];  // measured ns per pair and anti-diagonal (0: not tuned)
     int n_launch_last;              // launches of the last timed call
+    int lanes;                      // streams the persistent launches spread over
+    hipStream_t side[MAX_LANES - 1];
+    hipEvent_t fork_ev, join_ev[MAX_LANES - 1];
     int launch_class[NGROUP];       // their kernel classes
     int32_t *h_counts;              // pinned host copy of the group sizes (bucketed schedule)
     hipEvent_t ev[NEVENTS];
@@ -1464,6 +1475,7 @@ int ga_context_create(ga_context_t **out, int device) {
     ctx->device = device;
     ctx->class_mask = ALL_CLASSES;
     ctx->class_order = DEFAULT_ORDER;
+    ctx->lanes = MAX_LANES;
     if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         ctx->num_cu = 256;
     // persistent grids: as many workgroups as the registers let reside
@@ -1498,6 +1510,11 @@ int ga_context_destroy(ga_context_t *ctx) {
     hipDeviceSynchronize();
     if (ctx->ev[0])
         for (int k = 0; k < NEVENTS; ++k) hipEventDestroy(ctx->ev[k]);
+    for (int k = 0; k < MAX_LANES - 1; ++k) {
+        if (ctx->side[k]) hipStreamDestroy(ctx->side[k]);
+        if (ctx->join_ev[k]) hipEventDestroy(ctx->join_ev[k]);
+    }
+    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->d_err) hipFree(ctx->d_err);
     if (ctx->h_counts) hipHostFree(ctx->h_counts);
@@ -1534,13 +1551,15 @@ int ga_context_timing(ga_context_t *ctx, float *ms, int n) {
     if (!ctx || !ms || n < 1) return GA_EINVAL;
     if (!ctx->timed_last) return GA_EINVAL;
     SetDevice sd(ctx->device);
-    if (hipEventSynchronize(ctx->ev[1 + ctx->n_launch_last]) != hipSuccess) return GA_EHIP;
+    for (int l = 0; l < ctx->n_launch_last; ++l)
+        if (hipEventSynchronize(ctx->ev[3 + 2 * l]) != hipSuccess) return GA_EHIP;
+    if (hipEventSynchronize(ctx->ev[1]) != hipSuccess) return GA_EHIP;
     for (int k = 0; k < n; ++k) ms[k] = 0.f;
     float t = 0.f;
     if (hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]) != hipSuccess) return GA_EHIP;
     ms[0] = t;
     for (int l = 0; l < ctx->n_launch_last; ++l) {
-        if (hipEventElapsedTime(&t, ctx->ev[1 + l], ctx->ev[2 + l]) != hipSuccess) return GA_EHIP;
+        if (hipEventElapsedTime(&t, ctx->ev[2 + 2 * l], ctx->ev[3 + 2 * l]) != hipSuccess) return GA_EHIP;
         const int c = ctx->launch_class[l];
         if (1 + c < n) ms[1 + c] += t;
     }
@@ -1552,6 +1571,12 @@ int ga_context_set_schedule(ga_context_t *ctx, int schedule) {
                  schedule != GA_SCHED_UNORDERED))
         return GA_EINVAL;
     ctx->schedule = schedule;
+    return GA_OK;
+}
+
+int ga_context_set_lanes(ga_context_t *ctx, int lanes) {
+    if (!ctx || lanes < 1 || lanes > MAX_LANES) return GA_EINVAL;
+    ctx->lanes = lanes;
     return GA_OK;
 }
 
@@ -1898,21 +1923,51 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
             const int c = cnt > 0 ? bucket_class(g, w, ctx->class_mask) : -1;
             if (c < 0) continue;
             da.group = g;
+            if (timed) hipEventRecord(ctx->ev[2 + 2 * nl], s);
             launch_class(c, da, cnt, s);
+            if (timed) hipEventRecord(ctx->ev[3 + 2 * nl], s);
             ctx->launch_class[nl] = c;
             ++nl;
-            if (timed) hipEventRecord(ctx->ev[1 + nl], s);
         }
     } else {
+        // fork the context's streams off the caller's, launch each class on
+        // its lane, join them back: the classes' launches overlap, so the
+        // tail of one (its last long pairs) runs beside the others
+        const int L = ctx->lanes;
+        hipStream_t lane_s[MAX_LANES] = {s, s, s};
+        if (L > 1) {
+            if (!ctx->fork_ev) {
+                if (hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess) {
+                    ctx->fork_ev = nullptr;
+                    return GA_EHIP;
+                }
+                for (int k = 0; k < MAX_LANES - 1; ++k)
+                    if (hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking) != hipSuccess ||
+                        hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming) != hipSuccess)
+                        return GA_EHIP;
+            }
+            if (hipEventRecord(ctx->fork_ev, s) != hipSuccess) return GA_EHIP;
+            for (int k = 1; k < L; ++k) {
+                if (hipStreamWaitEvent(ctx->side[k - 1], ctx->fork_ev, 0) != hipSuccess) return GA_EHIP;
+                lane_s[k] = ctx->side[k - 1];
+            }
+        }
         for (int c = 0; c < NCLASS; ++c) {
             if (!((ctx->class_mask >> c) & 1u)) continue;
             const int64_t want = (int64_t)ctx->num_cu * ctx->blocks_per_cu[c];
             const int grid = (int)(np < want ? np : want);
+            hipStream_t ls = lane_s[LANE_OF[c] % L];
             da.group = c;
-            launch_class(c, da, grid, s);
+            if (timed) hipEventRecord(ctx->ev[2 + 2 * nl], ls);
+            launch_class(c, da, grid, ls);
+            if (timed) hipEventRecord(ctx->ev[3 + 2 * nl], ls);
             ctx->launch_class[nl] = c;
             ++nl;
-            if (timed) hipEventRecord(ctx->ev[1 + nl], s);
+        }
+        for (int k = 1; k < L; ++k) {
+            if (hipEventRecord(ctx->join_ev[k - 1], ctx->side[k - 1]) != hipSuccess ||
+                hipStreamWaitEvent(s, ctx->join_ev[k - 1], 0) != hipSuccess)
+                return GA_EHIP;
         }
     }
     ctx->n_launch_last = nl;

@@ -66,6 +66,9 @@ class _Slot:
                  graphs: bool = True):
         self.lib = load_library()
         self.ctx = Context(device)
+        # one stream per slot: the slots already overlap, and more streams
+        # than the GPU's hardware queues would serialise unrelated batches
+        self.ctx.set_lanes(1)
         self.stream = _torch().cuda.Stream(device=device)  # default priority
         self.device = device
         self.scoring, self.w, self.Z = dict(scoring), int(w), int(Z)

@@ -537,15 +537,17 @@ def test_graph_replays_match_eager():
     rng = np.random.default_rng(53)
     sc = dict(seqgen.SCORING)
     slot = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=True)
+    forked = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=True)
+    forked.ctx.set_lanes(3)  # the captured graph forks and joins the context's streams
     eager = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=False)
     for k, n in enumerate([16, 1, 9, 16, 5]):
         b = seqgen.random_pairs(rng, n, 0, 700, err=0.1, n_rate=0.01, related=0.8, w=200, zdrop=150)
         reqs = [serve._Request(i, b.target(i), b.query(i), 0.0) for i in range(n)]
         _say(f"graph replay {k}: {n} pairs")
-        for s in (slot, eager):
+        for s in (slot, forked, eager):
             s.launch(reqs)
         got = {}
-        for name, s in (("graph", slot), ("eager", eager)):
+        for name, s in (("graph", slot), ("forked", forked), ("eager", eager)):
             for _ in range(20000):
                 r = s.poll()
                 if r is not None:
@@ -554,6 +556,7 @@ def test_graph_replays_match_eager():
                 time.sleep(0.0005)
         assert slot.graph is not None and eager.graph is None
         assert np.array_equal(got["graph"], got["eager"]), k
+        assert np.array_equal(got["forked"], got["eager"]), k
         assert np.array_equal(got["graph"], gpu_align(b)), k
         want, _ = oracle_align(b)
         assert_same(got["graph"], want, b, f"graph replay {k}")
@@ -561,8 +564,8 @@ def test_graph_replays_match_eager():
         x = torch.arange(1 << 20, device="cuda", dtype=torch.int32)
         assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
         torch.cuda.synchronize()
-    slot.ctx.close()
-    eager.ctx.close()
+    for s in (slot, forked, eager):
+        s.ctx.close()
 
 
 def test_autotune_order_and_results():
@@ -594,4 +597,34 @@ def test_autotune_order_and_results():
     ctx.check()
     want, _ = oracle_align(b)
     assert_same(out.cpu().numpy(), want, b, "autotuned cfg1")
+    ctx.close()
+
+
+def test_lanes_same_results():
+    """Spreading the class launches over one, two or three streams gives the
+    same results (checked against the oracle on a mixed sample)."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    full = seqgen.make_config(3, n_pairs=3000, seed=4)
+    b = full.subset(np.nonzero(full.t_len <= 6000)[0][:1500])
+    ctx = ga.Context(0)
+    lib = ga.load_library()
+    assert lib.ga_context_set_lanes(ctx._h, 0) == ga.GA_EINVAL
+    assert lib.ga_context_set_lanes(ctx._h, 4) == ga.GA_EINVAL
+    packed = ga.pack_batch(ctx, b)
+    outs = []
+    for lanes in (1, 2, 3):
+        ctx.set_lanes(lanes)
+        ctx.set_timing(True)
+        out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+        torch.cuda.synchronize()
+        ctx.check()
+        ms = ctx.timing()
+        assert all(x >= 0 for x in ms) and sum(ms[1:]) > 0
+        outs.append(out.cpu().numpy())
+        _say(f"lanes {lanes}: {b.n_pairs} pairs, stages {[round(x, 3) for x in ms]}")
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    want, _ = oracle_align(b)
+    assert_same(outs[2], want, b, "lanes")
     ctx.close()
