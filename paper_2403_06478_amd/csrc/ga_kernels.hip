@@ -1147,14 +1147,37 @@ struct PlanArgs {
     ga_result_t *out;
 };
 
+// Add 1 to ctr[key] for every lane of the wave with key >= 0, with one
+// atomic per distinct key in the wave (a batch's pairs crowd into few
+// (class, cost bucket) keys, and contended atomics on one address
+// serialise). Returns, for such a lane, the counter's old value plus the
+// lane's rank among the wave's lanes with its key, so the values handed out
+// are distinct. Every lane of the wave must take part.
+__device__ __forceinline__ int wave_counter_inc(int32_t *ctr, int key) {
+    const int lane = __lane_id();
+    uint64_t todo = __ballot(key >= 0);
+    int pos = -1;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int k = __shfl(key, leader);
+        const uint64_t same = __ballot(key == k) & todo;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&ctr[k], (int)__popcll(same));
+        base = __shfl(base, leader);
+        if ((same >> lane) & 1ull) pos = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
+    return pos;
+}
+
 // Validate each pair, finish invalid and empty pairs, and give the rest a
 // (group, cost bucket) key. Persistent schedule: the group is the cheapest
 // class that runs the pair (class_for) and the cost bucket orders each group
 // longest first. Bucketed schedule: the group is the power-of-two bucket of
-// max(n, m), with no ordering inside it.
-__global__ void ga_plan_classify(PlanArgs A) {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= A.n_pairs) return;
+// max(n, m), with no ordering inside it. The key of pair p is -1 when the
+// pair is finished here (invalid, empty or held by no allowed class; its
+// result is written).
+__device__ __forceinline__ int plan_key(const PlanArgs &A, int64_t p) {
     const int32_t n = A.t_len[p], m = A.q_len[p];
     const int64_t to = A.t_off[p], qo = A.q_off[p];
     const bool bad = n < 0 || m < 0 || n > A.max_len || m > A.max_len || to < 0 || qo < 0 ||
@@ -1180,10 +1203,19 @@ __global__ void ga_plan_classify(PlanArgs A) {
             A.out[p] = ga_result_t{0, -1, -1, 0, -1, -1, -1};
         } else {
             key = group * PLAN_BUCKETS + bucket;
-            atomicAdd(&A.hist[key], 1);
         }
     }
-    A.keys[p] = key;
+    return key;
+}
+
+__global__ void ga_plan_classify(PlanArgs A) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int key = -1;
+    if (p < A.n_pairs) {
+        key = plan_key(A, p);
+        A.keys[p] = key;
+    }
+    wave_counter_inc(A.hist, key);
 }
 
 // One workgroup of 1024 threads: list positions of every (group, cost
@@ -1229,11 +1261,9 @@ __global__ __launch_bounds__(1024) void ga_plan_scan(PlanArgs A) {
 
 __global__ void ga_plan_scatter(PlanArgs A) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= A.n_pairs) return;
-    const int key = A.keys[p];
-    if (key < 0) return;
-    const int pos = atomicAdd(&A.cursor[key], 1);
-    A.lists[pos] = (int32_t)p;
+    const int key = p < A.n_pairs ? A.keys[p] : -1;
+    const int pos = wave_counter_inc(A.cursor, key);
+    if (key >= 0) A.lists[pos] = (int32_t)p;
 }
 
 // ---- packing: ASCII -> 2-bit stream + N bitmap (input packing, Section 2.2)
