@@ -95,6 +95,13 @@ int ga_context_destroy(ga_context_t *ctx);
  * (such pairs get the result {0,-1,-1,0,-1,-1,-1}). */
 int ga_context_check(ga_context_t *ctx, void *stream);
 
+/* The device address of pinned host memory (allocated with hipHostMalloc,
+ * or as a pinned torch tensor), for callers that let the kernels read their
+ * inputs and write their results in place (zero-copy staging): every *_dev
+ * pointer of this interface may be such an address. GA_EINVAL (and NULL)
+ * if `host` is not pinned host memory. */
+int ga_host_device_pointer(void *host, void **dev);
+
 /* Human-readable text for a GA_* code (static storage). */
 const char *ga_strerror(int code);
 

@@ -32,7 +32,8 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_pack_words", "ga_pack", "ga_align_batch", "ga_count_cells",
                "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
                "ga_calibrate_valu", "ga_context_set_schedule", "ga_context_set_classes",
-               "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class", "ga_context_set_lanes")
+               "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class", "ga_context_set_lanes",
+               "ga_host_device_pointer")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
@@ -122,6 +123,8 @@ def load_library() -> ctypes.CDLL:
     lib.ga_pair_class_in.restype = ctypes.c_int
     lib.ga_context_set_classes.argtypes = [vp, ctypes.c_uint32]
     lib.ga_context_set_classes.restype = ctypes.c_int
+    lib.ga_host_device_pointer.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.ga_host_device_pointer.restype = ctypes.c_int
     lib.ga_context_set_lanes.argtypes = [vp, ctypes.c_int]
     lib.ga_context_set_lanes.restype = ctypes.c_int
     lib.ga_context_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int, vp]
@@ -318,6 +321,14 @@ def ga_align_batch(ctx: Context, packed: PackedBatch, scoring: dict, w: int, Z: 
 
 def ga_pair_class(n: int, m: int, w: int) -> int:
     return int(load_library().ga_pair_class(int(n), int(m), int(w)))
+
+
+def host_device_pointer(host_ptr: int) -> int:
+    """Device address of pinned host memory (raises if it is not pinned)."""
+    dev = ctypes.c_void_p()
+    _check(load_library().ga_host_device_pointer(ctypes.c_void_p(host_ptr), ctypes.byref(dev)),
+           "ga_host_device_pointer")
+    return int(dev.value)
 
 
 def ga_pair_class_in(n: int, m: int, w: int, classes) -> int:

@@ -1317,6 +1317,7 @@ __global__ void ga_pack_kernel(const uint8_t *ascii, const int64_t *off, const i
     const int32_t L = len[p];
     const int64_t wo = word_off[p];
     const int64_t nw = L > 0 ? ((int64_t)L + 15) / 16 : 0;
+    const uint8_t *src = ascii + off[p];
     for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) {
         const int64_t gw = wo + k;
         if (gw < 0 || gw >= nwords) {
@@ -1324,12 +1325,26 @@ __global__ void ga_pack_kernel(const uint8_t *ascii, const int64_t *off, const i
             continue;
         }
         uint32_t v = 0, nb = 0;
-        for (int b = 0; b < 16; ++b) {
-            const int64_t pos = 16 * k + b;
-            if (pos >= L) break;
-            bool is_n;
-            v |= base2bit(ascii[off[p] + pos], is_n) << (2 * b);
-            nb |= (is_n ? 1u : 0u) << b;
+        const uint8_t *s16 = src + 16 * k;
+        if (16 * k + 16 <= L && (reinterpret_cast<uintptr_t>(s16) & 15) == 0) {
+            // a whole word of bases at an aligned address: one 16-byte load
+            // (one bus transaction when the bytes sit in host memory)
+            const uint4 q = *reinterpret_cast<const uint4 *>(s16);
+            const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                bool is_n;
+                v |= base2bit((uint8_t)(w4[b >> 2] >> (8 * (b & 3))), is_n) << (2 * b);
+                nb |= (is_n ? 1u : 0u) << b;
+            }
+        } else {
+            for (int b = 0; b < 16; ++b) {
+                const int64_t pos = 16 * k + b;
+                if (pos >= L) break;
+                bool is_n;
+                v |= base2bit(s16[b], is_n) << (2 * b);
+                nb |= (is_n ? 1u : 0u) << b;
+            }
         }
         words[gw] = v;
         if (nb) atomicOr(&nmask[gw >> 1], nb << (16 * (gw & 1)));
@@ -1601,6 +1616,17 @@ int ga_context_set_schedule(ga_context_t *ctx, int schedule) {
                  schedule != GA_SCHED_UNORDERED))
         return GA_EINVAL;
     ctx->schedule = schedule;
+    return GA_OK;
+}
+
+int ga_host_device_pointer(void *host, void **dev) {
+    if (!host || !dev) return GA_EINVAL;
+    *dev = nullptr;
+    if (hipHostGetDevicePointer(dev, host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        *dev = nullptr;
+        return GA_EINVAL;
+    }
     return GA_OK;
 }
 

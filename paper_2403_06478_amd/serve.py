@@ -1,18 +1,26 @@
 """Continuous-batching serving loop over the C ABI.
 
-Requests (one target/query pair each) arrive over time. The server keeps a
-FIFO of admitted requests and a few execution slots; each slot owns a
-context (its own device workspace) and a HIP stream. Whenever a slot is
-free, the requests waiting at that moment form its next batch, up to a pair
-count and a memory footprint (bases staged on the device), and the batch is
-packed, aligned and copied back on the slot's stream. Slots run
-concurrently, so requests that arrive while other batches are on the GPU are
-admitted as soon as a slot frees up and their work overlaps on the device
-with the batches already running. A request's latency runs from its arrival
-to the moment the host sees its batch complete.
+Requests (one target/query pair each) arrive over time. Each lane of the
+server (short requests, long requests) keeps a request ring in pinned,
+host-coherent memory that the GPU reads in place: requests are admitted
+when their bytes fit in the ring (admission by memory footprint), in groups
+of at most a batch, each group written once; until then they wait in the
+lane's host FIFO. A few execution slots per lane each own a context (its
+own device workspace) and a HIP stream. Whenever a slot is free, the
+admitted requests waiting at that moment form its next batch, up to a pair
+count and a number of bases: the slot writes their ring offsets and
+lengths into its pinned tables and replays one captured HIP graph that
+packs both sides straight out of the ring and aligns them, the kernels
+reading the tables and writing the results in pinned memory in place; no
+bytes are copied per batch. Slots run concurrently, so requests
+that arrive while other batches are on the GPU are admitted and batched as
+soon as memory and a slot free up, and their work overlaps on the device
+with the batches already running. A request's latency runs from its
+arrival to the moment the host sees its batch complete; its ring space is
+released once every request of its group is done.
 
 Every step of the alignment runs in the HIP library; this module only
-schedules batches and moves bytes.
+schedules batches and places bytes.
 
 ``python -m paper_2403_06478_amd.serve`` runs the serving benchmark: the
 request mix of ``seqgen`` workload 5 with Poisson arrivals at given
@@ -33,7 +41,7 @@ from typing import List, Optional
 import numpy as np
 
 from . import (Batch, Context, _check, _stream_handle, _torch, count_cells, ga_align_batch,
-               load_library, pack_batch, scoring_struct)
+               host_device_pointer, load_library, pack_batch, scoring_struct)
 
 
 @dataclasses.dataclass
@@ -42,149 +50,238 @@ class _Request:
     target: bytes
     query: bytes
     t_arrival: float
+    off: int = -1  # ring offset of the target (the query follows it); -1 until admitted
+    region: int = -1  # the ring region holding it (shared by the requests admitted together)
+
+
+def _pad16(n: int) -> int:
+    return (n + 15) & ~15
+
+
+_ZPAD = [bytes(k) for k in range(16)]  # zero padding to the next 16-byte boundary
+
+
+class RingSpace:
+    """Space of a ring of `capacity` bytes handed out contiguously in
+    arrival order (a request that does not fit before the end starts again
+    at 0, the skipped end counting as used) and released in any order; the
+    oldest released regions are reclaimed as soon as everything older is
+    released too. Bookkeeping only (host side)."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.head = 0  # next free byte
+        self.used = 0  # bytes between the oldest live region and head, skipped ends included
+        self.regions = collections.deque()  # [offset, size, released] in allocation order
+        self.live = {}  # offset -> its region, while in use
+
+    def alloc(self, size: int) -> int:
+        """Offset of `size` contiguous bytes, or -1 if they do not fit now."""
+        size = max(int(size), 1)
+        if size > self.capacity:
+            raise ValueError(f"{size} bytes exceed the ring ({self.capacity} bytes)")
+        if self.used == 0:
+            self.head = 0
+        tail = (self.head - self.used) % self.capacity  # the oldest live byte
+        if self.used < self.capacity and self.head >= tail:
+            if self.capacity - self.head >= size:  # room before the end
+                off = self.head
+            elif tail >= size:  # wrap: skip the end
+                skipped = self.capacity - self.head
+                self.regions.append([self.head, skipped, True])
+                self.used += skipped
+                off = 0
+            else:
+                return -1
+        elif self.used < self.capacity and tail - self.head >= size:  # the gap between head and tail
+            off = self.head
+        else:
+            return -1
+        reg = [off, size, False]
+        self.regions.append(reg)
+        self.live[off] = reg
+        self.head = (off + size) % self.capacity
+        self.used += size
+        return off
+
+    def release(self, off: int):
+        self.live.pop(off)[2] = True
+        while self.regions and self.regions[0][2]:
+            self.used -= self.regions.popleft()[1]
+
+
+class RequestRing:
+    """The request queue of a lane: request bytes in pinned, host-coherent
+    memory that the packing kernel reads in place (no copy to device memory:
+    each byte crosses the bus once, when its batch is packed), laid out by a
+    RingSpace. Requests are admitted in groups of at most a batch, each
+    group written once into its own region, which is released when all of
+    its requests are done."""
+
+    def __init__(self, capacity: int):
+        torch = _torch()
+        self.space = RingSpace(_pad16(capacity))
+        self.capacity = self.space.capacity
+        self.buf = torch.zeros(self.capacity, dtype=torch.uint8, pin_memory=True)
+        self.view = self.buf.numpy()
+        # the address kernels use for the pinned buffer
+        self.ptr = host_device_pointer(self.buf.data_ptr())
+        self.refs = {}  # region offset -> requests in it not yet released
+
+    def release(self, req: _Request):
+        """The request is done: its region goes back once all of its
+        requests are."""
+        left = self.refs[req.region] - 1
+        if left:
+            self.refs[req.region] = left
+        else:
+            del self.refs[req.region]
+            self.space.release(req.region)
+
+    def admit(self, reqs, max_group: int) -> int:
+        """Place the longest prefix of `reqs` (at most max_group requests)
+        that fits now in one region, each request's target then its query,
+        each starting on a 16-byte boundary (the packer then reads whole
+        words of bases in one transaction); returns how many were placed."""
+        sizes = [((len(r.target) + 15) & ~15) + ((len(r.query) + 15) & ~15) for r in reqs[:max_group]]
+        k = len(sizes)
+        total = sum(sizes)
+        free = self.capacity - self.space.used
+        while k and total > free:  # a prefix that may fit
+            k -= 1
+            total -= sizes[k]
+        off = -1
+        while k:
+            off = self.space.alloc(total)
+            if off >= 0:
+                break
+            k //= 2
+            total = sum(sizes[:k])
+        if k == 0:
+            return 0
+        if total:
+            parts = []
+            for r in reqs[:k]:
+                parts += (r.target, _ZPAD[-len(r.target) & 15], r.query, _ZPAD[-len(r.query) & 15])
+            self.view[off:off + total] = np.frombuffer(b"".join(parts), dtype=np.uint8)
+        pos = off
+        for r, sz in zip(reqs[:k], sizes):
+            r.off, r.region = pos, off
+            pos += sz
+        self.refs[off] = k
+        return k
 
 
 class _Slot:
-    """One execution slot: a context (own device workspace), a HIP stream,
-    and staging buffers sized once for the largest batch -- pinned host
-    buffers for the request bytes and results, device buffers for the packed
-    streams -- so a batch allocates nothing (an allocation can synchronise
-    the device and stall every other slot).
+    """One execution slot of a lane: a context (own device workspace, one
+    stream for all its launches), a HIP stream, pinned tables of ring
+    offsets and lengths and a pinned result table, all sized once for the
+    slot's largest batch. With ``graphs`` the device steps of a batch
+    (packing both sides out of the ring and the alignment) are one captured
+    HIP graph replayed per batch: every batch is presented at the slot's
+    capacity (unused pair entries are empty pairs, which the planner
+    finishes at once; the packed streams are declared at their full
+    capacity), so one graph serves batches of any size."""
 
-    With ``graphs`` the device steps of a batch (packing both sides and the
-    alignment) are one captured HIP graph, launched once per batch: every
-    batch is presented at the slot's capacity (the unused pair entries are
-    empty pairs, which the planner finishes at once, and the packed streams
-    are declared at their full capacity), so the same graph serves every
-    batch; only the request bytes, offsets and lengths are copied in before
-    the launch and the used results copied out after it."""
-
-    # longest sequence a captured batch declares (the bound its range guard checks)
-    GRAPH_MAX_LEN = 1 << 20
-
-    def __init__(self, device: int, max_pairs: int, max_bases: int, scoring: dict, w: int, Z: int,
-                 graphs: bool = True):
+    def __init__(self, device: int, ring: RequestRing, max_pairs: int, scoring: dict, w: int, Z: int,
+                 graphs: bool = True, lanes: int = 1):
+        torch = _torch()
         self.lib = load_library()
         self.ctx = Context(device)
-        # one stream per slot: the slots already overlap, and more streams
-        # than the GPU's hardware queues would serialise unrelated batches
-        self.ctx.set_lanes(1)
-        self.stream = _torch().cuda.Stream(device=device)  # default priority
-        self.device = device
+        # one stream per slot by default: the slots already overlap, and more
+        # streams than the GPU's hardware queues would serialise unrelated
+        # batches
+        self.ctx.set_lanes(lanes)
+        self.stream = torch.cuda.Stream(device=device)  # default priority
+        self.ring = ring
         self.scoring, self.w, self.Z = dict(scoring), int(w), int(Z)
-        self.graphs = bool(graphs)
-        self.graph = None
-        self.max_pairs = self.max_bases = 0
-        self._size(max_pairs, max_bases)
-        self.reqs: Optional[List[_Request]] = None
-        self.event = None
-
-    def _size(self, max_pairs: int, max_bases: int):
-        """(Re)allocate the staging buffers for batches of up to max_pairs
-        pairs and max_bases bases per side (and drop the captured graph,
-        which names the old buffers). Only an oversized request makes a slot
-        grow after start."""
-        torch = _torch()
-        dev = torch.device("cuda", self.device)
-        self.graph = None
-        self.max_pairs, self.max_bases = P, B = int(max(max_pairs, 1)), int(max(max_bases, 1))
-        self.W = W = B // 16 + P + 1  # 2-bit words of one side: at most sum of ceil(len / 16)
+        self.P = P = int(max(max_pairs, 1))
+        # words of one side: at most sum of ceil(len / 16) over the batch
+        self.W = W = ring.capacity // 16 + P + 1
+        self.max_len = min(ring.capacity, 1 << 20)  # the bound the captured call declares
+        dev = torch.device("cuda", device)
         pin = dict(pin_memory=True)
-        self.h_ascii = [torch.empty(B, dtype=torch.uint8, **pin) for _ in range(2)]
-        # unused entries stay empty pairs (offset 0, length 0)
         self.h_off = [torch.zeros(P, dtype=torch.int64, **pin) for _ in range(2)]
         self.h_len = [torch.zeros(P, dtype=torch.int32, **pin) for _ in range(2)]
-        self.h_out = torch.empty((P, 7), dtype=torch.int32, **pin)
-        self.d_ascii = [torch.zeros(B, dtype=torch.uint8, device=dev) for _ in range(2)]
-        self.d_off = [torch.zeros(P, dtype=torch.int64, device=dev) for _ in range(2)]
-        self.d_len = [torch.zeros(P, dtype=torch.int32, device=dev) for _ in range(2)]
+        self.h_out = torch.zeros((P, 7), dtype=torch.int32, **pin)
+        # addresses the kernels use for the pinned tables
+        self.p_off = [host_device_pointer(t.data_ptr()) for t in self.h_off]
+        self.p_len = [host_device_pointer(t.data_ptr()) for t in self.h_len]
+        self.p_out = host_device_pointer(self.h_out.data_ptr())
         self.d_words = [torch.zeros(W, dtype=torch.int32, device=dev) for _ in range(2)]
         self.d_woff = [torch.zeros(P, dtype=torch.int64, device=dev) for _ in range(2)]
         self.d_nmask = [torch.zeros((W + 1) // 2, dtype=torch.int32, device=dev) for _ in range(2)]
-        self.d_out = torch.empty((P, 7), dtype=torch.int32, device=dev)
-        torch.cuda.synchronize(self.device)
-
-    def _device_steps(self, st: int, n: int, nwords, max_len: int):
-        """Pack both sides and align n pairs, all enqueued on stream st."""
-        for side in range(2):
-            _check(self.lib.ga_pack(self.ctx.handle, self.d_ascii[side].data_ptr(), self.d_off[side].data_ptr(),
-                                    self.d_len[side].data_ptr(), n, nwords[side], self.d_words[side].data_ptr(),
-                                    self.d_woff[side].data_ptr(), self.d_nmask[side].data_ptr(), st), "ga_pack")
-        bt = Batch()
-        bt.n_pairs = n
-        bt.t_words_dev, bt.t_nwords = self.d_words[0].data_ptr(), nwords[0]
-        bt.q_words_dev, bt.q_nwords = self.d_words[1].data_ptr(), nwords[1]
-        bt.t_off_dev, bt.q_off_dev = self.d_woff[0].data_ptr(), self.d_woff[1].data_ptr()
-        bt.t_len_dev, bt.q_len_dev = self.d_len[0].data_ptr(), self.d_len[1].data_ptr()
-        bt.t_nmask_dev, bt.q_nmask_dev = self.d_nmask[0].data_ptr(), self.d_nmask[1].data_ptr()
-        bt.max_len = int(max_len)
-        sc = scoring_struct(self.scoring)
-        _check(self.lib.ga_align_batch(self.ctx.handle, ctypes.byref(bt), ctypes.byref(sc), self.w, self.Z,
-                                       self.d_out.data_ptr(), st), "ga_align_batch")
-
-    def _capture(self):
-        """Capture the capacity-shaped device steps (after one eager run on
-        the empty staging, which sizes the context's workspace)."""
-        torch = _torch()
-        shape = (self.max_pairs, [self.W, self.W], min(self.max_bases, self.GRAPH_MAX_LEN))
+        torch.cuda.synchronize(device)
+        # one run on empty pairs sizes the context's workspace for the capacity
         with torch.cuda.stream(self.stream):
-            self._device_steps(_stream_handle(self.stream), *shape)
+            self._device_steps(_stream_handle(self.stream))
         self.stream.synchronize()
         _check(self.lib.ga_context_check(self.ctx.handle, _stream_handle(self.stream)), "ga_context_check")
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=self.stream):
-            self._device_steps(_stream_handle(torch.cuda.current_stream()), *shape)
-        self.graph = g
+        self.graph = None
+        if graphs:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=self.stream):
+                self._device_steps(_stream_handle(torch.cuda.current_stream()))
+            self.graph = g
+        self.reqs: Optional[List[_Request]] = None
+        self.event = None
+
+    def _device_steps(self, st: int):
+        """Pack both sides out of the ring and align, at the slot's
+        capacity, all enqueued on stream st (nothing is copied)."""
+        for side in range(2):
+            _check(self.lib.ga_pack(self.ctx.handle, self.ring.ptr, self.p_off[side],
+                                    self.p_len[side], self.P, self.W, self.d_words[side].data_ptr(),
+                                    self.d_woff[side].data_ptr(), self.d_nmask[side].data_ptr(), st), "ga_pack")
+        bt = Batch()
+        bt.n_pairs = self.P
+        bt.t_words_dev, bt.t_nwords = self.d_words[0].data_ptr(), self.W
+        bt.q_words_dev, bt.q_nwords = self.d_words[1].data_ptr(), self.W
+        bt.t_off_dev, bt.q_off_dev = self.d_woff[0].data_ptr(), self.d_woff[1].data_ptr()
+        bt.t_len_dev, bt.q_len_dev = self.p_len[0], self.p_len[1]
+        bt.t_nmask_dev, bt.q_nmask_dev = self.d_nmask[0].data_ptr(), self.d_nmask[1].data_ptr()
+        bt.max_len = self.max_len
+        sc = scoring_struct(self.scoring)
+        _check(self.lib.ga_align_batch(self.ctx.handle, ctypes.byref(bt), ctypes.byref(sc), self.w, self.Z,
+                                       self.p_out, st), "ga_align_batch")
 
     @property
     def busy(self) -> bool:
         return self.reqs is not None
 
     def launch(self, reqs: List[_Request]):
+        """Start a batch of admitted requests (at most the slot's pairs)."""
         torch = _torch()
         n = len(reqs)
-        lens = [np.array([len(r.target) for r in reqs], dtype=np.int32),
-                np.array([len(r.query) for r in reqs], dtype=np.int32)]
-        bases = max(int(lens[0].sum()), int(lens[1].sum()))
-        if n > self.max_pairs or bases > self.max_bases:
-            self._size(max(n, self.max_pairs), max(bases, self.max_bases))
-        max_len = int(max(lens[0].max(initial=0), lens[1].max(initial=0)))
-        use_graph = self.graphs and max_len <= self.GRAPH_MAX_LEN
-        if use_graph and self.graph is None:
-            self._capture()
-        P = self.max_pairs if use_graph else n
+        if n > self.P:
+            raise ValueError("batch larger than the slot")
+        t_off, q_off = self.h_off[0].numpy(), self.h_off[1].numpy()
+        t_len, q_len = self.h_len[0].numpy(), self.h_len[1].numpy()
+        offs = np.fromiter((r.off for r in reqs), dtype=np.int64, count=n)
+        nt = np.fromiter((len(r.target) for r in reqs), dtype=np.int32, count=n)
+        t_off[:n], t_len[:n] = offs, nt
+        q_off[:n] = offs + ((nt.astype(np.int64) + 15) & ~15)
+        q_len[:n] = np.fromiter((len(r.query) for r in reqs), dtype=np.int32, count=n)
+        t_off[n:], t_len[n:], q_off[n:], q_len[n:] = 0, 0, 0, 0
         with torch.cuda.stream(self.stream):
-            for side in range(2):
-                seqs = b"".join(r.target if side == 0 else r.query for r in reqs)
-                off = np.zeros(n, dtype=np.int64)
-                off[1:] = np.cumsum(lens[side][:-1], dtype=np.int64)
-                self.h_ascii[side].numpy()[:len(seqs)] = np.frombuffer(seqs, dtype=np.uint8)
-                h_off, h_len = self.h_off[side].numpy(), self.h_len[side].numpy()
-                h_off[:n] = off
-                h_len[:n] = lens[side]
-                h_off[n:P] = 0
-                h_len[n:P] = 0
-                nb = max(len(seqs), 1)
-                self.d_ascii[side][:nb].copy_(self.h_ascii[side][:nb], non_blocking=True)
-                self.d_off[side][:P].copy_(self.h_off[side][:P], non_blocking=True)
-                self.d_len[side][:P].copy_(self.h_len[side][:P], non_blocking=True)
-            if use_graph:
+            if self.graph is not None:
                 self.graph.replay()
             else:
-                nwords = [int(self.lib.ga_pack_words(l.ctypes.data, n)) for l in lens]
-                self._device_steps(_stream_handle(self.stream), n, nwords, max_len)
-            self.h_out[:n].copy_(self.d_out[:n], non_blocking=True)
+                self._device_steps(_stream_handle(self.stream))
             self.event = torch.cuda.Event()
             self.event.record(self.stream)
         self.reqs = reqs
 
     def poll(self):
-        """(requests, results) once the batch has completed, else None."""
+        """(requests, results) once the batch has completed, else None; the
+        requests' ring space is released then."""
         if self.reqs is None or not self.event.query():
             return None
         _check(self.lib.ga_context_check(self.ctx.handle, _stream_handle(self.stream)), "ga_context_check")
         reqs = self.reqs
         res = self.h_out.numpy()[:len(reqs)].copy()
+        for r in reqs:
+            self.ring.release(r)
         self.reqs = self.event = None
         return reqs, res
 
@@ -194,59 +291,43 @@ class Server:
 
     A request whose bases (target + query) exceed ``long_bases`` goes to the
     long lane, every other request to the short lane, so short requests never
-    wait behind a long pair's sweep. Each lane has its own FIFO and slots
-    (``slots`` short, ``long_slots`` long). A short batch holds up to
-    ``max_batch_pairs`` pairs and ``max_batch_bases`` bases; a long batch up
-    to ``long_batch_pairs`` pairs and ``long_batch_bases`` bases (a long pair
-    runs on one workgroup for the whole of its sweep, so a long batch should
-    take every long request waiting). A request larger than its lane's base limit still forms a batch
-    of its own. Each slot's staging is sized once, at start, for its largest
-    batch.
+    wait behind a long pair's sweep. Each lane has its own request ring, FIFO
+    and slots (``slots`` short, ``long_slots`` long). A short batch holds up
+    to ``max_batch_pairs`` pairs and ``max_batch_bases`` bases; a long batch
+    up to ``long_batch_pairs`` pairs and ``long_batch_bases`` bases (a long
+    pair runs on one workgroup for the whole of its sweep, so a long batch
+    should take every long request waiting). A request larger than its
+    lane's batch limit still forms a batch of its own. The rings hold
+    ``ring_factor`` times a lane's batch limit; a request larger than its
+    ring is refused.
 
     HIP spreads streams over a few hardware queues (four by default) and the
-    kernels of streams that share a queue run one after another, so a short
-    batch would wait behind a long sweep; the defaults keep the slot streams
-    at three."""
+    work of streams that share a queue runs in order, so a short batch would
+    wait behind a long sweep; the defaults keep the slot streams at three
+    and the server adds no other stream (the rings are read in place)."""
 
     def __init__(self, scoring: dict, w: int, Z: int, device: int = 0, slots: int = 2,
                  long_slots: int = 1, max_batch_pairs: int = 256, max_batch_bases: int = 1_000_000,
                  long_bases: int = 8000, long_batch_pairs: int = 4096, long_batch_bases: int = 16_000_000,
-                 graphs: bool = True):
+                 graphs: bool = True, ring_factor: int = 4):
         self.scoring, self.w, self.Z = dict(scoring), int(w), int(Z)
         self.pairs = [int(max_batch_pairs), int(long_batch_pairs)]
         self.limits = [int(max_batch_bases), int(long_batch_bases)]
-        self.lanes = [[_Slot(device, self.pairs[k], self.limits[k], scoring, w, Z, graphs) for _ in range(n)]
+        self.rings = [RequestRing(ring_factor * lim) for lim in self.limits]
+        self.lanes = [[_Slot(device, self.rings[k], self.pairs[k], scoring, w, Z, graphs) for _ in range(n)]
                       for k, n in enumerate((slots, long_slots))]
         self.long_bases = int(long_bases)
-        self.pending = [collections.deque(), collections.deque()]
+        self.waiting = [collections.deque(), collections.deque()]   # not yet in the ring
+        self.admitted = [collections.deque(), collections.deque()]  # in the ring, not yet batched
         self.batches = 0
-        self._warm(device)
-
-    def _warm(self, device: int):
-        """Run one full-size batch through every slot so no later batch
-        grows a workspace (which would synchronise the device). The warm-up
-        pairs put the lane's bases in the targets and one base in each
-        query, so their sweep stops at the band's edge (or, unbanded, after
-        at most a few thousand anti-diagonals)."""
-        torch = _torch()
-        rng = np.random.default_rng(0)
-        acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
-        for lane, P, limit in zip(self.lanes, self.pairs, self.limits):
-            L = max(1, limit // P - 1)
-            if self.w < 0:
-                L = min(L, 4000)
-            seq = rng.choice(acgt, L).tobytes()
-            reqs = [_Request(-1, seq, b"A", 0.0) for _ in range(P)]
-            for slot in lane:
-                slot.launch(reqs)
-        torch.cuda.synchronize(device)
-        for lane in self.lanes:
-            for slot in lane:
-                slot.poll()
 
     def submit(self, rid: int, target: bytes, query: bytes, t_arrival: Optional[float] = None):
         lane = 1 if len(target) + len(query) > self.long_bases else 0
-        self.pending[lane].append(_Request(rid, target, query,
+        ring = self.rings[lane]
+        if (_pad16(len(target)) + _pad16(len(query)) > ring.capacity
+                or max(len(target), len(query)) > self.lanes[lane][0].max_len):
+            raise ValueError(f"request {rid} is larger than its lane's ring")
+        self.waiting[lane].append(_Request(rid, target, query,
                                            time.perf_counter() if t_arrival is None else t_arrival))
 
     @staticmethod
@@ -262,7 +343,8 @@ class Server:
         return reqs
 
     def step(self):
-        """Collect finished batches, then start batches on free slots.
+        """Collect finished batches (releasing their ring space), admit
+        waiting requests into the rings, then start batches on free slots.
         Returns [(rid, result row, t_done)] for the requests that finished."""
         done = []
         for lane in self.lanes:
@@ -272,18 +354,26 @@ class Server:
                     t = time.perf_counter()
                     reqs, res = got
                     done.extend((r.rid, res[k], t) for k, r in enumerate(reqs))
-        for lane, q, P, limit in zip(self.lanes, self.pending, self.pairs, self.limits):
+        for ring, wq, aq, P in zip(self.rings, self.waiting, self.admitted, self.pairs):
+            while wq:
+                k = ring.admit([wq[i] for i in range(min(len(wq), P))], P)
+                if not k:
+                    break
+                for _ in range(k):
+                    aq.append(wq.popleft())
+        for lane, aq, P, limit in zip(self.lanes, self.admitted, self.pairs, self.limits):
             for slot in lane:
-                if not q:
+                if not aq:
                     break
                 if not slot.busy:
-                    slot.launch(self._take_batch(q, P, limit))
+                    slot.launch(self._take_batch(aq, P, limit))
                     self.batches += 1
         return done
 
     @property
     def idle(self) -> bool:
-        return not any(self.pending) and not any(s.busy for lane in self.lanes for s in lane)
+        return (not any(self.waiting) and not any(self.admitted)
+                and not any(s.busy for lane in self.lanes for s in lane))
 
     def close(self):
         for lane in self.lanes:

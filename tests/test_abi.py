@@ -160,3 +160,42 @@ def test_fasta_reader(tmp_path):
     qry.write_bytes(b">q1\nACGT\n")
     with pytest.raises(ValueError):
         cli.make_batch(str(ref), str(qry), dict(a=2, b=4, q=4, e=2, q2=24, e2=1, ambig=1), 10, 10)
+
+
+def test_ring_space():
+    """The serving ring's allocator: live regions are contiguous, inside the
+    ring and disjoint; space comes back once everything older is released;
+    a full ring refuses and an empty one restarts at 0."""
+    import numpy as np
+
+    from paper_2403_06478_amd.serve import RingSpace
+    rng = np.random.default_rng(8)
+    for cap in (64, 1000, 4096):
+        sp = RingSpace(cap)
+        live = {}
+        for _ in range(4000):
+            if live and (rng.random() < 0.45 or len(live) > 40):
+                off = list(live)[int(rng.integers(0, len(live)))] if rng.random() < 0.5 else min(live, key=lambda o: live[o][1])
+                sp.release(off)
+                del live[off]
+            else:
+                size = int(rng.integers(1, max(2, cap // 3)))
+                off = sp.alloc(size)
+                if off < 0:
+                    assert live  # only a ring with live regions refuses
+                    continue
+                assert 0 <= off and off + size <= cap
+                for o, (sz, _) in live.items():
+                    assert off + size <= o or o + sz <= off, (off, size, o, sz)
+                live[off] = (size, len(live))
+            assert 0 <= sp.used <= cap
+        for off in list(live):
+            sp.release(off)
+        assert sp.used == 0 and not sp.regions and not sp.live
+        assert sp.alloc(cap) == 0  # an empty ring restarts at 0
+    try:
+        RingSpace(10).alloc(11)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("oversized request accepted")

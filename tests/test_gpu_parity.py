@@ -386,9 +386,11 @@ def test_serving_isolation():
     from paper_2403_06478_amd import serve
     b = seqgen.make_config(5, n_pairs=160, seed=3)
     arrivals = np.cumsum(np.random.default_rng(31).exponential(1.0 / 3000.0, size=b.n_pairs))
+    # small rings (twice a batch) so requests wait for ring space and the
+    # ring wraps around
     res, lat, wall, nb = serve.serve_trace(b, arrivals, slots=2, long_slots=1, max_batch_pairs=8,
                                            max_batch_bases=6000, long_batch_pairs=8,
-                                           long_batch_bases=40000)
+                                           long_batch_bases=40000, ring_factor=2)
     _say(f"served {b.n_pairs} requests in {nb} batches, {wall * 1e3:.1f} ms, p99 {np.percentile(lat, 99) * 1e3:.2f} ms")
     assert nb > 3
     assert np.all(lat > 0)
@@ -525,10 +527,11 @@ def test_cli_fasta(tmp_path):
 
 
 def test_graph_replays_match_eager():
-    """A serving slot replays one captured HIP graph (packing and alignment at
-    the slot's capacity) for batches of different sizes; every replay, with
-    eager work and synchronisation between replays, equals the eager call
-    on the same pairs and the oracle."""
+    """A serving slot replays one captured HIP graph (packing out of the
+    pinned request ring and aligning, at the slot's capacity) for batches of
+    different sizes; every replay, with eager work and synchronisation
+    between replays, equals the eager path on the same requests and the
+    oracle. One slot's graph forks the context's streams."""
     import time
 
     import torch
@@ -536,25 +539,26 @@ def test_graph_replays_match_eager():
     from paper_2403_06478_amd import serve
     rng = np.random.default_rng(53)
     sc = dict(seqgen.SCORING)
-    slot = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=True)
-    forked = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=True)
-    forked.ctx.set_lanes(3)  # the captured graph forks and joins the context's streams
-    eager = serve._Slot(0, 16, 12000, sc, 200, 150, graphs=False)
+    slots = {}
+    for name, graphs, lanes in (("graph", True, 1), ("forked", True, 3), ("eager", False, 1)):
+        slots[name] = serve._Slot(0, serve.RequestRing(30000), 16, sc, 200, 150, graphs=graphs, lanes=lanes)
     for k, n in enumerate([16, 1, 9, 16, 5]):
         b = seqgen.random_pairs(rng, n, 0, 700, err=0.1, n_rate=0.01, related=0.8, w=200, zdrop=150)
-        reqs = [serve._Request(i, b.target(i), b.query(i), 0.0) for i in range(n)]
         _say(f"graph replay {k}: {n} pairs")
-        for s in (slot, forked, eager):
-            s.launch(reqs)
         got = {}
-        for name, s in (("graph", slot), ("forked", forked), ("eager", eager)):
+        for name, slot in slots.items():
+            reqs = [serve._Request(i, b.target(i), b.query(i), 0.0) for i in range(n)]
+            assert slot.ring.admit(reqs, 16) == n
+            slot.launch(reqs)
+        for name, slot in slots.items():
             for _ in range(20000):
-                r = s.poll()
+                r = slot.poll()
                 if r is not None:
                     got[name] = r[1]
                     break
                 time.sleep(0.0005)
-        assert slot.graph is not None and eager.graph is None
+            assert slot.ring.space.used == 0  # the batch's ring space is released
+        assert slots["graph"].graph is not None and slots["eager"].graph is None
         assert np.array_equal(got["graph"], got["eager"]), k
         assert np.array_equal(got["forked"], got["eager"]), k
         assert np.array_equal(got["graph"], gpu_align(b)), k
@@ -564,40 +568,8 @@ def test_graph_replays_match_eager():
         x = torch.arange(1 << 20, device="cuda", dtype=torch.int32)
         assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
         torch.cuda.synchronize()
-    for s in (slot, forked, eager):
-        s.ctx.close()
-
-
-def test_autotune_order_and_results():
-    """The autotuner measures every class; afterwards each pair takes the
-    cheapest (by the measured costs) allowed class that runs it, and the
-    results stay those of the default order and the oracle."""
-    import torch
-
-    import paper_2403_06478_amd as ga
-    ctx = ga.Context(0)
-    cost = ctx.autotune()
-    _say("autotune: " + ", ".join(f"{ga.class_name(c)}={cost[c]:.3f}" for c in range(len(cost))))
-    assert len(cost) == len(ga.CLASSES) and all(np.isfinite(cost)) and min(cost) > 0
-    rng = np.random.default_rng(61)
-    every = range(len(ga.CLASSES))
-    for _ in range(2000):
-        n, m = (int(x) for x in rng.integers(1, 9000, 2))
-        w = int(rng.choice([-1, 50, 300, 751, 1000, 1500, 2500, 3500]))
-        holders = [c for c in every if ga.ga_pair_class_in(n, m, w, [c]) == c]
-        got = ctx.pair_class(n, m, w)
-        if not holders:
-            assert got == -1
-            continue
-        assert got in holders and cost[got] == min(cost[c] for c in holders), (n, m, w, got, holders)
-    b = seqgen.make_config(1)
-    packed = ga.pack_batch(ctx, b)
-    out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
-    torch.cuda.synchronize()
-    ctx.check()
-    want, _ = oracle_align(b)
-    assert_same(out.cpu().numpy(), want, b, "autotuned cfg1")
-    ctx.close()
+    for slot in slots.values():
+        slot.ctx.close()
 
 
 def test_lanes_same_results():
