@@ -126,7 +126,7 @@ int ga_pack(ga_context_t *ctx, const uint8_t *ascii_dev, const int64_t *off_dev,
  * (w < 0: no band) and z-drop threshold Z (Z < 0: never drop), writing
  * out_dev[p] for each pair. Range guard (GA_EINVAL otherwise):
  * (2*max_len + 2) * (max(a, b, ambig, q+e, q2+e2) + a + e + e2) + max(Z,0) < 2^29.
- * Band widths with 2*min(w, max_len) + 1 > 8192 return GA_EUNSUPPORTED. */
+ * Band widths with 2*min(w, max_len) + 1 > 8180 return GA_EUNSUPPORTED. */
 int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
                    int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);
 /* Graph capture: under GA_SCHED_PERSISTENT (and GA_SCHED_UNORDERED) with
@@ -207,10 +207,11 @@ int ga_context_set_timing(ga_context_t *ctx, int enable);
  * ms[1+c] = the alignment launches of class c (summed over buckets under
  * GA_SCHED_BUCKETED), for c < n-1 and c < 11. Class
  * c runs K slots per lane and W waves per pair: (K, W) = (4,1) (8,1) (16,1)
- * (24,1) (32,1) hold bands of up to 64*K*W diagonals; (8,1) (16,1) with a
+ * (24,1) (32,1) hold bands of up to 64*K diagonals; (8,1) (16,1) with a
  * sliding window run pairs whose shorter sequence s has 2s + 11 + K <= 64K
- * whatever the band; (24,2) (32,2) (32,3) (32,4) hold bands of up to 64*K*W
- * diagonals.
+ * whatever the band; (24,2) (32,2) (32,3) (32,4) hold bands of up to
+ * 64*K + (W-1)*(64*K - 4) diagonals (3068, 4092, 6136, 8180: neighbouring
+ * waves share 4 diagonals).
  * GA_EINVAL if timing was off for that call. */
 int ga_context_timing(ga_context_t *ctx, float *ms, int n);
 

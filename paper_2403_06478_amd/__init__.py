@@ -46,7 +46,14 @@ SCHEDULES = {"persistent": GA_SCHED_PERSISTENT, "bucketed": GA_SCHED_BUCKETED, "
 CLASSES = ((4, 1, False), (8, 1, False), (16, 1, False), (24, 1, False), (32, 1, False),
            (8, 1, True), (16, 1, True), (24, 2, False), (32, 2, False), (32, 3, False), (32, 4, False))
 CLASS_SLOTS = tuple(k for k, _, _ in CLASSES)
-MAX_DIAGONALS = 64 * 32 * 4
+def class_capacity(c: int) -> int:
+    """Diagonals class c holds: 64 K on one wave; neighbouring waves of a
+    multi-wave class overlap by 4 diagonals (their ghost copies)."""
+    k, nw, _ = CLASSES[c]
+    return 64 * k + (nw - 1) * (64 * k - 4)
+
+
+MAX_DIAGONALS = class_capacity(len(CLASSES) - 1)
 
 
 def class_name(c: int) -> str:

@@ -51,7 +51,8 @@ constexpr int PADB = 64;                         // guard bytes around the unpac
 constexpr int WAVE = 64;
 
 // Slot classes: K slots per lane and NW waves per pair hold the band's
-// D <= 64*K*NW diagonals; a pair goes to the first class that holds it.
+// D <= class_cap diagonals (64*K on one wave, less 4 per extra wave for the
+// shared ghost diagonals); a pair goes to the first class that holds it.
 constexpr int NCLASS = 11;
 // (K, NW, window) = (4,1,fixed) (8,1,fixed) (16,1,fixed) (24,1,fixed)
 // (32,1,fixed) (8,1,sliding) (16,1,sliding) (24,2,fixed) (32,2,fixed)
@@ -61,14 +62,22 @@ __host__ __device__ constexpr int class_k(int c) {
 }
 __host__ __device__ constexpr int class_nw(int c) { return c < 7 ? 1 : c < 9 ? 2 : c == 9 ? 3 : 4; }
 __host__ __device__ constexpr bool class_slides(int c) { return c == 5 || c == 6; }
-__host__ __device__ constexpr int class_cap(int c) { return WAVE * class_k(c) * class_nw(c); }
-constexpr int MAX_DIAGONALS = WAVE * 32 * 4;
+// Neighbouring waves of one pair overlap by 2*HALO diagonals: each holds
+// copies ("ghosts") of the HALO diagonals next to its edge, refreshed from
+// their owner every HALO anti-diagonals, so the waves exchange state and
+// meet at a barrier only every HALO anti-diagonals.
+constexpr int HALO = 2;
+__host__ __device__ constexpr int wave_stride(int K) { return WAVE * K - 2 * HALO; }
+__host__ __device__ constexpr int class_cap(int c) {
+    return WAVE * class_k(c) + (class_nw(c) - 1) * wave_stride(class_k(c));
+}
+constexpr int MAX_DIAGONALS = WAVE * 32 + 3 * wave_stride(32);
 
 constexpr uint32_t ALL_CLASSES = (1u << NCLASS) - 1;
 
 // The class a pair runs in, and whether its one wave slides along the band
 // (*slide = -1 down, +1 up, 0 fixed). A band of D diagonals fits class c when
-// D <= 64*K*NW. When one sequence is short, an anti-diagonal's cells from the
+// D <= class_cap(c). When one sequence is short, an anti-diagonal's cells from the
 // boundary cell to the cell just past the short sequence's end span at most
 // 2*min(n,m) + 3 diagonals; a single wave whose window follows them (moved
 // one lane at a time, hence the K of slack) runs such a pair even when the
@@ -101,7 +110,9 @@ __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *s
         const int c = (int)((order >> (4 * k)) & 0xFull);
         if (!((mask >> c) & 1u)) continue;
         if (!class_slides(c)) {
-            if (D <= class_cap(c) && D > WAVE * class_k(c) * (class_nw(c) - 1)) return c;
+            const int K = class_k(c), NW = class_nw(c);
+            const int64_t below = NW > 1 ? WAVE * K + (NW - 2) * wave_stride(K) : 0;  // NW-1 waves' reach
+            if (D <= class_cap(c) && D > below) return c;
         } else if (D > class_cap(c) && span + class_k(c) <= class_cap(c)) {
             *slide = n <= m ? -1 : 1;
             return c;
@@ -348,9 +359,14 @@ struct Track {
 template <int K, int NW>
 struct PairLds {
     int park[K * WAVE];  // park[s * 64 + lane] = A of slot s
-    int edge[2][NW][3];
-    int ma[2][NW];
+    // several waves (double-buffered by exchange): the owned edge diagonals
+    // a wave hands its neighbours (A, E, X, F, Y of two slots each way) and
+    // the wave maxima of the exchange's two anti-diagonals
+    int up[2][NW][2][5];
+    int dn[2][NW][2][5];
+    int ma[2][NW][2];
     int ma2[NW];         // wave maxima of an anti-diagonal redone with masks
+    int flag;            // a rare decision's outcome, for every wave
     int idx;             // pair index handed to every wave
 };
 
@@ -524,40 +540,30 @@ __device__ __forceinline__ int finish_diag(const PairState<K> &st, const DpArgs 
     return last ? 1 : 0;
 }
 
-// Several waves per pair, after the class-C update of anti-diagonal r. One
-// barrier per anti-diagonal: each wave publishes its maximum, then all read
-// every wave's maximum and take the same decisions from the same values.
-// The rare events that need a cell (the last anti-diagonal, a z-drop
-// candidate) are handled by the wave holding the anti-diagonal maximum
-// alone: it resolves the cells, runs the test, writes the pair's result and,
-// on a z-drop, publishes STOP in place of its maximum at the next
-// anti-diagonal, where every wave then stops (the extra anti-diagonal they
-// computed is never looked at). Returns true when done.
+// Several waves per pair: the decisions for anti-diagonal r (class C) after
+// the exchange that published every wave's maximum of it (slot `k` of the
+// exchange buffers `b`). All waves read the same maxima and take the same
+// decisions. The rare events that need a cell (the last anti-diagonal, a
+// z-drop candidate) are resolved by the wave holding the anti-diagonal
+// maximum (the lowest such wave: the smallest diagonal, hence the smallest
+// i): after a barrier that makes every park visible, it locates the cells,
+// runs the test and writes the pair's result, then tells every wave the
+// outcome through LDS and a second barrier. Returns true when done.
 template <int K, int C, int NW>
-__device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArgs &P, const Geo &g,
-                                             Track &tr, int r, int lane, int wv, PairLds<K, NW> &S,
-                                             int p, bool ring) {
-    // unmasked lane maxima: outside the rectangle only the two boundary
-    // cells can be finite (the cells past either end are clamped)
-    int lm = lane_max<K, C, NW>(st, g, 0, 0, false);
-    int MAw = wave_max(lm);
-    const int b = r & 1;
-    if (lane == 0) S.ma[b][wv] = tr.stop ? STOP : MAw;
-    __syncthreads();
+__device__ __forceinline__ bool decide_mw(const PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
+                                          int r, int lm, int lane, int wv, PairLds<K, NW> &S, int p, int b,
+                                          int k, bool ring) {
     // LDS loads land in VGPRs: readfirstlane keeps the decisions scalar
-    int MA = __builtin_amdgcn_readfirstlane(S.ma[b][0]);
-    int vstar = 0;  // lowest wave holding MA: the smallest diagonal, hence the smallest i
-    bool stop = MA == STOP;
+    int MA = __builtin_amdgcn_readfirstlane(S.ma[b][0][k]);
+    int vstar = 0;
 #pragma unroll
-    for (int k = 1; k < NW; ++k) {
-        const int x = __builtin_amdgcn_readfirstlane(S.ma[b][k]);
-        stop = stop || x == STOP;
+    for (int v = 1; v < NW; ++v) {
+        const int x = __builtin_amdgcn_readfirstlane(S.ma[b][v][k]);
         if (x > MA) {
             MA = x;
-            vstar = k;
+            vstar = v;
         }
     }
-    if (stop) return true;
     const bool last = r >= g.r_last;
     int vlo = 0, vhi = 0;
     bool masked = false;
@@ -566,19 +572,20 @@ __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArg
         masked = true;
         diag_window(g, r, vlo, vhi);
         lm = vlo <= vhi ? lane_max<K, C, NW>(st, g, vlo, vhi, true) : NEG_MAX;
-        MAw = wave_max(lm);
+        const int MAw = wave_max(lm);
         if (lane == 0) S.ma2[wv] = MAw;
         __syncthreads();
         MA = __builtin_amdgcn_readfirstlane(S.ma2[0]);
         vstar = 0;
 #pragma unroll
-        for (int k = 1; k < NW; ++k) {
-            const int x = __builtin_amdgcn_readfirstlane(S.ma2[k]);
+        for (int v = 1; v < NW; ++v) {
+            const int x = __builtin_amdgcn_readfirstlane(S.ma2[v]);
             if (x > MA) {
                 MA = x;
-                vstar = k;
+                vstar = v;
             }
         }
+        __syncthreads();  // S.ma2 is reused by the next redo
     }
     if (MA <= LIVE_MIN) return last;  // no interior cell on this anti-diagonal
     const int M = MA + P.q1 - P.e1 * r;  // back to the true score
@@ -587,13 +594,14 @@ __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArg
         if (wv == vstar) park_class<K, C, NW>(st, S, lane);
         tr.G = M;
         tr.g_r = r;
-        tr.g_base = g.a0 + vstar * (WAVE * K);
+        tr.g_base = g.a0 + vstar * wave_stride(K);
         tr.g_cls = C;
         tr.g_ma = MA;
         tr.g_set = true;
     }
     const bool cand = !up && P.Z >= 0 && tr.G - M > P.Z;
     if (!(cand || last)) return false;
+    __syncthreads();  // every park so far is visible to the wave resolving
     if (wv == vstar) {
         if (!masked) diag_window(g, r, vlo, vhi);
         int mi, mj, gi = -1, gj = -1;
@@ -615,48 +623,67 @@ __device__ __forceinline__ bool post_step_mw(const PairState<K> &st, const DpArg
                 const int v[7] = {tr.G, gi, gj, M, mi, mj, drop ? 1 : 0};
                 int val = v[0];
 #pragma unroll
-                for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
+                for (int t = 1; t < 7; ++t) val = (lane == t) ? v[t] : val;
                 reinterpret_cast<int32_t *>(P.out + p)[lane] = val;
             }
-            tr.stop = drop;
         }
+        if (lane == 0) S.flag = (drop || last) ? 1 : 0;
     }
-    return last;
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(S.flag) != 0;
 }
 
-// Several waves per pair: after the class-C update of anti-diagonal r, publish
-// the edge values the neighbouring wave needs for anti-diagonal r+1 ...
-template <int K, int C, int NW>
-__device__ __forceinline__ void publish_edges(const PairState<K> &st, PairLds<K, NW> &S, int r, int lane,
-                                              int wv) {
-    const int b = r & 1;
-    if (C == 1) {  // slot K-1 of lane 63 is the upper wave's "up" neighbour
-        if (wv < NW - 1 && lane == WAVE - 1) {
-            S.edge[b][wv][0] = st.A[K - 1];
-            S.edge[b][wv][1] = st.E[K - 1];
-            S.edge[b][wv][2] = st.X[K - 1];
+// Several waves per pair, at an exchange: each wave hands its neighbours
+// the owned diagonals next to their ghosts -- slots K-4, K-3 of lane 63 go
+// up, slots 2, 3 of lane 0 go down -- with their latest values.
+template <int K, int NW>
+__device__ __forceinline__ void publish_ghosts(const PairState<K> &st, PairLds<K, NW> &S, int b, int lane,
+                                               int wv) {
+    if (wv < NW - 1 && lane == WAVE - 1) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            S.up[b][wv][t][0] = st.A[K - 4 + t];
+            S.up[b][wv][t][1] = st.E[K - 4 + t];
+            S.up[b][wv][t][2] = st.X[K - 4 + t];
+            S.up[b][wv][t][3] = st.F[K - 4 + t];
+            S.up[b][wv][t][4] = st.Y[K - 4 + t];
         }
-    } else {  // slot 0 of lane 0 is the lower wave's "left" neighbour
-        if (wv > 0 && lane == 0) {
-            S.edge[b][wv][0] = st.A[0];
-            S.edge[b][wv][1] = st.F[0];
-            S.edge[b][wv][2] = st.Y[0];
+    }
+    if (wv > 0 && lane == 0) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            S.dn[b][wv][t][0] = st.A[2 + t];
+            S.dn[b][wv][t][1] = st.E[2 + t];
+            S.dn[b][wv][t][2] = st.X[2 + t];
+            S.dn[b][wv][t][3] = st.F[2 + t];
+            S.dn[b][wv][t][4] = st.Y[2 + t];
         }
     }
 }
 
-// ... and read them at the start of the class-C update of anti-diagonal r.
-template <int C, int K, int NW>
-__device__ __forceinline__ void read_edges(const PairLds<K, NW> &S, int r, int wv, int &f0, int &f1,
-                                           int &f2) {
-    f0 = f1 = f2 = NEG;
-    if constexpr (NW > 1) {
-        const int b = (r - 1) & 1;
-        const int src = C == 0 ? wv - 1 : wv + 1;
-        if (src >= 0 && src < NW) {
-            f0 = S.edge[b][src][0];
-            f1 = S.edge[b][src][1];
-            f2 = S.edge[b][src][2];
+// ... and, after the barrier, each wave refreshes its ghosts: slots 0, 1 of
+// lane 0 from the wave below, slots K-2, K-1 of lane 63 from the wave above.
+template <int K, int NW>
+__device__ __forceinline__ void read_ghosts(PairState<K> &st, const PairLds<K, NW> &S, int b, int lane,
+                                            int wv) {
+    if (wv > 0 && lane == 0) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            st.A[t] = S.up[b][wv - 1][t][0];
+            st.E[t] = S.up[b][wv - 1][t][1];
+            st.X[t] = S.up[b][wv - 1][t][2];
+            st.F[t] = S.up[b][wv - 1][t][3];
+            st.Y[t] = S.up[b][wv - 1][t][4];
+        }
+    }
+    if (wv < NW - 1 && lane == WAVE - 1) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            st.A[K - 2 + t] = S.dn[b][wv + 1][t][0];
+            st.E[K - 2 + t] = S.dn[b][wv + 1][t][1];
+            st.X[K - 2 + t] = S.dn[b][wv + 1][t][2];
+            st.F[K - 2 + t] = S.dn[b][wv + 1][t][3];
+            st.Y[K - 2 + t] = S.dn[b][wv + 1][t][4];
         }
     }
 }
@@ -749,7 +776,15 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
     return false;
 }
 
-// Several waves per pair, 8 anti-diagonals r0 .. r0+7, in order.
+// Several waves per pair, 8 anti-diagonals r0 .. r0+7 in four exchanges of
+// two. Each wave updates its slots (ghosts included) for both
+// anti-diagonals with -inf beyond its edge lanes -- a ghost fed -inf is at
+// most its true value, and the two ghost diagonals keep every owned
+// diagonal exact for two anti-diagonals -- then publishes its owned edge
+// diagonals and both wave maxima, meets the others at one barrier,
+// refreshes its ghosts and takes the decisions of both anti-diagonals in
+// order. Ghost values never exceed the true ones, so counting them in a
+// wave maximum changes nothing (the owner counts the true value).
 template <int K, int NW>
 __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, const Geo &g,
                                           Track &tr, int r0, int lane, int wv, uint64_t wall_lanes,
@@ -765,33 +800,47 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
     const uint32_t bits_j = step_bits(max(max(t0, g.a0 + 2 * g.m - r0), -pj0), WAVE * K - 1 - pj0);
     const uint32_t bits_w = wall_lanes != 0 ? ((wall_pos & 1) ? 0xAAu : 0x55u) & step_bits(t0, 7) : 0u;
     const uint32_t bits_ring = step_bits(t0, max(g.a1, -g.a0) - r0 - 2);
-#define GA_STEP(T)                                                                    \
+#define GA_HSTEP(T, LM, MAW)                                                          \
     {                                                                                 \
         constexpr int C = (T) & 1;                                                    \
         constexpr int KC = (T) >> 1;                                                  \
-        const int r = r0 + (T);                                                       \
-        if (r >= 0) {                                                                 \
-            int f0, f1, f2;                                                           \
-            read_edges<C, K, NW>(S, r, wv, f0, f1, f2);                               \
-            dp_step<K, C, KC>(st, P, f0, f1, f2);                                     \
+        if (r0 + (T) >= 0) {                                                          \
+            dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                  \
             if (bits_w & (1u << (T))) clamp_wall<K>(st, wall_lanes, wall_pos);        \
             if (bits_i & (1u << (T))) clamp_cell<K, true>(st, pi0 - (T));             \
             if (bits_j & (1u << (T))) clamp_cell<K, false>(st, pj0 + (T));            \
-            publish_edges<K, C, NW>(st, S, r, lane, wv);                              \
-            if (post_step_mw<K, C, NW>(st, P, g, tr, r, lane, wv, S, p,               \
-                                       (bits_ring & (1u << (T))) != 0))               \
-                return true;                                                          \
+            LM = lane_max<K, C, NW>(st, g, 0, 0, false);                              \
+            MAW = wave_max(LM);                                                       \
         }                                                                             \
     }
-    GA_STEP(0)
-    GA_STEP(1)
-    GA_STEP(2)
-    GA_STEP(3)
-    GA_STEP(4)
-    GA_STEP(5)
-    GA_STEP(6)
-    GA_STEP(7)
-#undef GA_STEP
+#define GA_EXCHANGE(T)                                                                \
+    {                                                                                 \
+        int lm0 = NEG_MAX, lm1 = NEG_MAX, ma0 = NEG_MAX, ma1 = NEG_MAX;               \
+        GA_HSTEP(T, lm0, ma0)                                                         \
+        GA_HSTEP((T) + 1, lm1, ma1)                                                   \
+        const int b = ((r0 + (T)) >> 1) & 1;                                          \
+        publish_ghosts<K, NW>(st, S, b, lane, wv);                                    \
+        if (lane == 0) {                                                              \
+            S.ma[b][wv][0] = ma0;                                                     \
+            S.ma[b][wv][1] = ma1;                                                     \
+        }                                                                             \
+        __syncthreads();                                                              \
+        read_ghosts<K, NW>(st, S, b, lane, wv);                                       \
+        if (r0 + (T) >= 0 &&                                                          \
+            decide_mw<K, 0, NW>(st, P, g, tr, r0 + (T), lm0, lane, wv, S, p, b, 0,    \
+                                (bits_ring & (1u << (T))) != 0))                      \
+            return true;                                                              \
+        if (r0 + (T) + 1 >= 0 &&                                                      \
+            decide_mw<K, 1, NW>(st, P, g, tr, r0 + (T) + 1, lm1, lane, wv, S, p, b, 1, \
+                                (bits_ring & (1u << ((T) + 1))) != 0))                \
+            return true;                                                              \
+    }
+    GA_EXCHANGE(0)
+    GA_EXCHANGE(2)
+    GA_EXCHANGE(4)
+    GA_EXCHANGE(6)
+#undef GA_EXCHANGE
+#undef GA_HSTEP
     return false;
 }
 
@@ -911,7 +960,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         g.a0 = -m;
         a1 = n;
     }
-    g.a0w = g.a0 + wv * (WAVE * K);
+    g.a0w = g.a0 + wv * wave_stride(K);
     g.dlo = max(g.a0, 1 - m);
     g.dhi = min(a1, n - 1);
     const int D = a1 - g.a0 + 1;
@@ -969,15 +1018,6 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
 
     const uint8_t *tbase = P.tb + 16 * P.t_off[p];
     const uint8_t *qbase = P.qb + 16 * P.q_off[p];
-    if constexpr (NW > 1) {
-        // the edges of anti-diagonal -1 for the first step (anti-diagonal 0,
-        // class 2 + r0, i.e. 0 when r0 = -2 and 1 when r0 = -1)
-        if (r0 == -2)
-            publish_edges<K, 1, NW>(st, S, -1, lane, wv);
-        else
-            publish_edges<K, 0, NW>(st, S, -1, lane, wv);
-        __syncthreads();
-    }
     Windows<K> wd;
     load_windows<K>(wd, tbase, qbase, n, m, r0, d0);
     int base_next = g.a0w;

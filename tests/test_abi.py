@@ -85,7 +85,7 @@ def test_pair_class_rule():
     order = [0, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10]
     for _ in range(3000):
         n, m = (int(x) for x in rng.integers(0, 9000, 2))
-        w = int(rng.choice([-1, 0, 1, 100, 751, 2000, 4095, 5000]))
+        w = int(rng.choice([-1, 0, 1, 100, 751, 1533, 1534, 2000, 2046, 3068, 4089, 4095, 5000]))
         got = ga.ga_pair_class(n, m, w)
         if n == 0 or m == 0:
             assert got == -1
@@ -95,14 +95,13 @@ def test_pair_class_rule():
         want = -1
         for c in order:
             k, nw, sl = ga.CLASSES[c]
-            cap = 64 * k * nw
+            cap = ga.class_capacity(c)
             if (not sl and D <= cap) or (sl and 2 * min(n, m) + 11 + k <= cap):
                 want = c
                 break
         assert got == want, (n, m, w, got, want)
         if got >= 0 and not ga.CLASSES[got][2]:
-            k, nw, _ = ga.CLASSES[got]
-            assert D <= 64 * k * nw
+            assert D <= ga.class_capacity(got)
 
 
 def test_pair_class_rule_restricted():
@@ -129,11 +128,12 @@ def test_pair_class_rule_restricted():
             if c not in allowed:
                 continue
             k, nw, sl = ga.CLASSES[c]
-            cap = 64 * k * nw
+            cap = ga.class_capacity(c)
             if sl:
                 ok = D > cap and 2 * min(n, m) + 11 + k <= cap
             else:
-                ok = 64 * k * (nw - 1) < D <= cap
+                below = 64 * k + (nw - 2) * (64 * k - 4) if nw > 1 else 0  # one wave fewer
+                ok = below < D <= cap
             if ok:
                 want = c
                 break
