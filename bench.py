@@ -59,15 +59,18 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
-    summary, or None if there is none for it or the kernel source changed
-    since it was taken."""
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from a committed
+    rocprofv3 --pmc summary, or None if there is none for them or the kernel
+    source changed since it was taken."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     text = open(PMC_SUMMARY).read()
     m = re.search(r"kernel:\s*(\S+)", text)
     if not m or m.group(1) != kernel:
+        return None
+    m = re.search(r"workload:\s*(\S+)", text)
+    if not m or m.group(1) != workload:
         return None
     m = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", text)
     if not m or m.group(1) != kernel_source_hash():
@@ -196,7 +199,7 @@ def main():
     dom = int(np.argmax(per_class))
     dom_cells = int(per_class[dom])
     achieved = OPS_PER_CELL * dom_cells / (mean_ms[1 + dom] / 1e3) / 1e12
-    traffic = read_traffic(ga.class_name(dom))
+    traffic = read_traffic(ga.class_name(dom), args.workload)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / PEAK_TOPS, 4), "traffic": traffic,
                 "kernel": ga.class_name(dom),
