@@ -17,9 +17,10 @@
 // completes a whole anti-diagonal, so the local maximum of Eq. 6 is one wave
 // reduction and the z-drop test of Eq. 5 runs in order with no run-ahead: the
 // rolling window of partial maxima (Section 4.1) and the slice boundary
-// (Section 4.2) are not needed. With several waves per pair, the waves swap
-// their edge slots and their maxima through LDS once per anti-diagonal,
-// around one workgroup barrier.
+// (Section 4.2) are not needed. With several waves per pair, neighbouring
+// waves share two ghost diagonals per edge and swap their edge slots and
+// their maxima through LDS once per two anti-diagonals, around one
+// workgroup barrier.
 //
 // Boundary cells (row -1 and column -1) are produced by the same recurrence:
 // the slots outside the rectangle start at -inf and the origin at 0, so the
@@ -30,7 +31,7 @@
 // Bases are unpacked once per batch from the 2-bit stream (plus N bitmap) to
 // one byte per base (0..3, N = 4). Per 8-step block each slot builds the
 // substitution scores of its next 4 cells with one v_perm_b32 table lookup
-// (4 signed bytes), and each cell extracts its byte with v_bfe_i32.
+// (4 signed bytes), and each cell adds its byte through an SDWA operand.
 
 #include <hip/hip_runtime.h>
 
@@ -348,14 +349,13 @@ struct Track {
     int g_r, g_base, g_cls, g_ma;  // g_base: diagonal of lane 0's slot 0 in the holding wave
     bool g_open;  // G moved since its cell was last resolved
     bool g_set;   // G has moved off the origin
-    bool stop;    // (several waves) this wave found the z-drop: tell the others
 };
 
 // LDS of one pair's workgroup: the park of the wave holding the global
 // maximum (slot-major, so 64 lanes write 64 consecutive words), and with
-// several waves per pair the per-anti-diagonal exchange, double buffered by
-// anti-diagonal parity: the edge values each wave publishes for its
-// neighbour's next step and each wave's maximum.
+// several waves per pair the exchange every two anti-diagonals, double
+// buffered: the owned edge diagonals each wave hands its neighbours' ghosts
+// and each wave's maxima.
 template <int K, int NW>
 struct PairLds {
     int park[K * WAVE];  // park[s * 64 + lane] = A of slot s
@@ -369,10 +369,6 @@ struct PairLds {
     int flag;            // a rare decision's outcome, for every wave
     int idx;             // pair index handed to every wave
 };
-
-// A wave maximum no cell can take: a wave publishes it in place of its
-// maximum to tell the others that the sweep has ended.
-constexpr int STOP = -2147483647 - 1;
 
 // Interior diagonals of anti-diagonal r, clipped to its parity.
 __device__ __forceinline__ void diag_window(const Geo &g, int r, int &vlo, int &vhi) {
@@ -1014,7 +1010,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
             }
         }
     }
-    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false, false};
+    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false};
 
     const uint8_t *tbase = P.tb + 16 * P.t_off[p];
     const uint8_t *qbase = P.qb + 16 * P.q_off[p];
