@@ -29,6 +29,13 @@
  * completed. Errors found on the device (a pair longer than the declared
  * bound, offsets outside the packed streams) are latched in the context and
  * reported by ga_context_check().
+ *
+ * A context serves one call at a time: its workspace (unpacked bases,
+ * planning counters, the error latch) is reused by every ga_pack and
+ * ga_align_batch on it, so calls on one context must be ordered on the
+ * device (issued on one stream, or with the caller's synchronisation
+ * between streams) and made from one host thread at a time. Work that
+ * should overlap uses one context per stream.
  */
 #ifndef GA_H
 #define GA_H
