@@ -247,6 +247,69 @@ int ga_calibrate_valu(ga_context_t *ctx, double *lane_ops_per_s, void *stream);
  * anti-diagonal, which is an interval of rows with closed-form ends. */
 int64_t ga_count_cells(int32_t n, int32_t m, int32_t w, int32_t r_end);
 
+/* ---------------------------------------------------------------------
+ * Native continuous-batching server (host runtime over the calls above).
+ *
+ * Requests (one target/query pair each) arrive over time. Each lane (short
+ * requests, and requests of more than long_bases bases) keeps a request
+ * ring in pinned host memory that the packing kernel reads in place; a
+ * request is admitted when its bytes fit (admission by memory footprint),
+ * in groups of at most a batch, and waits in the lane's FIFO until then.
+ * Each lane has its own execution slots; a slot owns a context (one stream
+ * for all its launches), a HIP stream, pinned tables and device streams
+ * sized for its capacity and, with `graphs`, one captured HIP graph of the
+ * capacity-shaped ga_pack + ga_pack + ga_align_batch, replayed per batch
+ * (unused pair entries are empty pairs). Whenever a slot is free, the
+ * admitted requests waiting in its lane form its next batch, up to
+ * max_batch_pairs pairs and max_batch_bases bases (long lane: long_*). A
+ * server is driven from one host thread. */
+typedef struct {
+    int32_t slots, long_slots;              /* execution slots per lane (>= 1) */
+    int32_t max_batch_pairs, long_batch_pairs;
+    int64_t max_batch_bases, long_batch_bases;
+    int32_t long_bases;                     /* requests with more bases go to the long lane */
+    int32_t ring_factor;                    /* ring bytes = ring_factor x the lane's batch bases */
+    int32_t graphs;                         /* 1: replay a captured graph per batch */
+} ga_server_config_t;
+
+typedef struct ga_server ga_server_t;
+
+/* Create a server on `device` for one scoring, band and threshold (see
+ * ga_align_batch). Allocates every buffer and captures the graphs now.
+ * GA_EINVAL for a bad configuration, GA_ENOMEM, GA_EHIP. */
+int ga_server_create(ga_server_t **srv, int device, const ga_scoring_t *sc, int32_t w, int32_t Z,
+                     const ga_server_config_t *cfg);
+
+/* Release the server (waits for its batches). */
+int ga_server_destroy(ga_server_t *srv);
+
+/* Queue one request (bytes are copied; any byte outside ACGTacgt is N).
+ * `tag` is returned with its result; t_arrival is its arrival time in
+ * seconds on the steady clock (negative: now). GA_EUNSUPPORTED for a
+ * request larger than its lane's ring or longer than 2^20 bases. */
+int ga_server_submit(ga_server_t *srv, int64_t tag, const uint8_t *target, int32_t n, const uint8_t *query,
+                     int32_t m, double t_arrival);
+
+/* Make progress without waiting: collect finished batches (writing up to
+ * max_done (tag, result, completion time) triples; a batch is collected
+ * only when all of it fits), admit waiting requests, start batches on free
+ * slots. Returns the number of results written, or a negative GA_* code
+ * (GA_EDEVICE if a device-side check failed for a collected batch). */
+int ga_server_poll(ga_server_t *srv, int64_t *tags, ga_result_t *results, double *t_done, int max_done);
+
+/* Requests submitted and not yet collected; batches launched so far. */
+int64_t ga_server_pending(const ga_server_t *srv);
+int64_t ga_server_batches(const ga_server_t *srv);
+
+/* Replay an arrival trace natively (the serving benchmark): request k --
+ * target bytes t_ascii[t_off[k] .. +t_len[k]), query likewise -- arrives
+ * arrival_s[k] seconds (non-decreasing) after the start; the call submits
+ * each at its time, polls until all are done and writes results[k] and
+ * latency_s[k] (arrival to collection), and the wall time. */
+int ga_server_replay(ga_server_t *srv, const uint8_t *t_ascii, const int64_t *t_off, const int32_t *t_len,
+                     const uint8_t *q_ascii, const int64_t *q_off, const int32_t *q_len, const double *arrival_s,
+                     int64_t n, ga_result_t *results, double *latency_s, double *wall_s);
+
 #ifdef __cplusplus
 }
 #endif

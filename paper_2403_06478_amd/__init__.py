@@ -33,7 +33,8 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_context_set_timing", "ga_context_timing", "ga_pair_class",
                "ga_calibrate_valu", "ga_context_set_schedule", "ga_context_set_classes",
                "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class", "ga_context_set_lanes",
-               "ga_host_device_pointer")
+               "ga_host_device_pointer", "ga_server_create", "ga_server_destroy", "ga_server_submit",
+               "ga_server_poll", "ga_server_pending", "ga_server_batches", "ga_server_replay")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
@@ -69,6 +70,15 @@ class GaError(RuntimeError):
 
 class Scoring(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in ("a", "b", "q", "e", "q2", "e2", "ambig")]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int32), ("long_slots", ctypes.c_int32),
+        ("max_batch_pairs", ctypes.c_int32), ("long_batch_pairs", ctypes.c_int32),
+        ("max_batch_bases", ctypes.c_int64), ("long_batch_bases", ctypes.c_int64),
+        ("long_bases", ctypes.c_int32), ("ring_factor", ctypes.c_int32), ("graphs", ctypes.c_int32),
+    ]
 
 
 class Batch(ctypes.Structure):
@@ -130,6 +140,22 @@ def load_library() -> ctypes.CDLL:
     lib.ga_pair_class_in.restype = ctypes.c_int
     lib.ga_context_set_classes.argtypes = [vp, ctypes.c_uint32]
     lib.ga_context_set_classes.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.ga_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(Scoring), i32, i32,
+                                     ctypes.POINTER(ServerConfig)]
+    lib.ga_server_create.restype = ctypes.c_int
+    lib.ga_server_destroy.argtypes = [vp]
+    lib.ga_server_destroy.restype = ctypes.c_int
+    lib.ga_server_submit.argtypes = [vp, i64, vp, i32, vp, i32, ctypes.c_double]
+    lib.ga_server_submit.restype = ctypes.c_int
+    lib.ga_server_poll.argtypes = [vp, vp, vp, vp, ctypes.c_int]
+    lib.ga_server_poll.restype = ctypes.c_int
+    lib.ga_server_pending.argtypes = [vp]
+    lib.ga_server_pending.restype = i64
+    lib.ga_server_batches.argtypes = [vp]
+    lib.ga_server_batches.restype = i64
+    lib.ga_server_replay.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, dp]
+    lib.ga_server_replay.restype = ctypes.c_int
     lib.ga_host_device_pointer.argtypes = [vp, ctypes.POINTER(vp)]
     lib.ga_host_device_pointer.restype = ctypes.c_int
     lib.ga_context_set_lanes.argtypes = [vp, ctypes.c_int]

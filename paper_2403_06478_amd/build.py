@@ -8,7 +8,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", "ga_kernels.hip")]
+SOURCES = [os.path.join(PKG, "csrc", "ga_kernels.hip"), os.path.join(PKG, "csrc", "ga_serve.hip")]
 LIB = os.path.join(PKG, "libga.so")
 
 HIPCC_FLAGS = [

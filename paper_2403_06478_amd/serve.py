@@ -40,7 +40,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import (Batch, Context, _check, _stream_handle, _torch, count_cells, ga_align_batch,
+from . import (Batch, Context, ServerConfig, _check, _stream_handle, _torch, count_cells, ga_align_batch,
                host_device_pointer, load_library, pack_batch, scoring_struct)
 
 
@@ -381,6 +381,70 @@ class Server:
                 s.ctx.close()
 
 
+class NativeServer:
+    """The native server (``ga_server_*`` in the library): the same lanes,
+    rings, slots and graphs as ``Server``, driven by a C++ host loop."""
+
+    def __init__(self, scoring: dict, w: int, Z: int, device: int = 0, slots: int = 2, long_slots: int = 1,
+                 max_batch_pairs: int = 256, max_batch_bases: int = 1_000_000, long_bases: int = 8000,
+                 long_batch_pairs: int = 4096, long_batch_bases: int = 16_000_000, graphs: bool = True,
+                 ring_factor: int = 4):
+        _torch()  # the HIP runtime torch uses, and a device
+        self.lib = load_library()
+        cfg = ServerConfig(int(slots), int(long_slots), int(max_batch_pairs), int(long_batch_pairs),
+                           int(max_batch_bases), int(long_batch_bases), int(long_bases), int(ring_factor),
+                           1 if graphs else 0)
+        sc = scoring_struct(scoring)
+        h = ctypes.c_void_p()
+        _check(self.lib.ga_server_create(ctypes.byref(h), int(device), ctypes.byref(sc), int(w), int(Z),
+                                         ctypes.byref(cfg)), "ga_server_create")
+        self._h = h
+
+    def replay(self, batch, arrivals: np.ndarray):
+        """Serve ``batch``'s pairs arriving at ``arrivals`` (seconds after the
+        start): (results [n, 7], latencies in seconds, wall seconds)."""
+        n = batch.n_pairs
+        arr = np.ascontiguousarray(arrivals, dtype=np.float64)
+        res = np.zeros((n, 7), dtype=np.int32)
+        lat = np.zeros(n, dtype=np.float64)
+        wall = ctypes.c_double(0.0)
+        t_seq = np.ascontiguousarray(batch.t_seq, dtype=np.uint8)
+        q_seq = np.ascontiguousarray(batch.q_seq, dtype=np.uint8)
+        t_off = np.ascontiguousarray(batch.t_off, dtype=np.int64)
+        q_off = np.ascontiguousarray(batch.q_off, dtype=np.int64)
+        t_len = np.ascontiguousarray(batch.t_len, dtype=np.int32)
+        q_len = np.ascontiguousarray(batch.q_len, dtype=np.int32)
+        _check(self.lib.ga_server_replay(self._h, t_seq.ctypes.data, t_off.ctypes.data, t_len.ctypes.data,
+                                         q_seq.ctypes.data, q_off.ctypes.data, q_len.ctypes.data, arr.ctypes.data,
+                                         n, res.ctypes.data, lat.ctypes.data, ctypes.byref(wall)),
+               "ga_server_replay")
+        return res, lat, float(wall.value)
+
+    @property
+    def batches(self) -> int:
+        return int(self.lib.ga_server_batches(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.ga_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_trace_native(batch, arrivals: np.ndarray, device: int = 0, **server_args):
+    """As serve_trace, with the native server."""
+    srv = NativeServer(batch.scoring, batch.w, batch.zdrop, device, **server_args)
+    res, lat, wall = srv.replay(batch, arrivals)
+    nb = srv.batches
+    srv.close()
+    return res, lat, wall, nb
+
+
 def serve_trace(batch, arrivals: np.ndarray, device: int = 0, **server_args):
     """Replay a request trace: request k (pair k of ``batch``) arrives at
     ``arrivals[k]`` seconds after the start. Returns (results [n, 7],
@@ -447,6 +511,8 @@ def main(argv=None):
     ap.add_argument("--long-batch-pairs", type=int, default=4096)
     ap.add_argument("--long-batch-bases", type=int, default=16_000_000)
     ap.add_argument("--no-graphs", action="store_true", help="enqueue each batch's steps eagerly")
+    ap.add_argument("--python", action="store_true", help="drive the slots from the Python loop (Server) "
+                    "instead of the native server")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args(argv)
     torch = _torch()
@@ -460,7 +526,8 @@ def main(argv=None):
     sys.stderr.write(f"[serve] offline: {batch.n_pairs} requests as one batch in {dt_off * 1e3:.1f} ms "
                      f"({batch.n_pairs / dt_off:.0f} req/s, {cells / dt_off / 1e9:.1f} GCUPS)\n")
     # the server's own capacity: every request waiting at the start
-    res_sat, lat_sat, wall_sat, nb_sat = serve_trace(batch, np.zeros(batch.n_pairs), **kw)
+    run = serve_trace if args.python else serve_trace_native
+    res_sat, lat_sat, wall_sat, nb_sat = run(batch, np.zeros(batch.n_pairs), **kw)
     capacity = batch.n_pairs / wall_sat
     sys.stderr.write(f"[serve] saturated: {wall_sat * 1e3:.1f} ms, {capacity:.0f} req/s, {nb_sat} batches, "
                      f"{cells / wall_sat / 1e9:.1f} GCUPS\n")
@@ -471,7 +538,7 @@ def main(argv=None):
         qps = frac * capacity
         rng = np.random.default_rng([5, args.seed, 1])
         arrivals = np.cumsum(rng.exponential(1.0 / qps, size=batch.n_pairs))
-        res, lat, wall, nb = serve_trace(batch, arrivals, **kw)
+        res, lat, wall, nb = run(batch, arrivals, **kw)
         same = bool(np.array_equal(res, res_off))
         line = {
             "metric": "serving latency", "unit": "ms", "qps": round(qps, 1), "rate_of_capacity": frac,
@@ -485,6 +552,7 @@ def main(argv=None):
             "gcups": round(cells / wall / 1e9, 3), "offline_gcups": round(cells / dt_off / 1e9, 3),
             "saturated_gcups": round(cells / wall_sat / 1e9, 3),
             "batches": nb, "wall_s": round(wall, 3), "same_as_offline": same, "graphs": not args.no_graphs,
+            "host_loop": "python" if args.python else "native",
             "workload": "seqgen workload 5: 95% pairs of 100-1000 bp (5% errors), 5% of 10-25 kb "
                         "(1% errors + indels), w=500, Z=400, Poisson arrivals",
         }

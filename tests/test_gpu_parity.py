@@ -600,3 +600,46 @@ def test_lanes_same_results():
     want, _ = oracle_align(b)
     assert_same(outs[2], want, b, "lanes")
     ctx.close()
+
+
+def test_native_server():
+    """The native server (C++ host loop over the same slots, rings and
+    graphs): a trace served through small rings gives the oracle's results,
+    the same as the Python loop's; submit and poll work one by one too."""
+    import time
+
+    import paper_2403_06478_amd as ga
+    from paper_2403_06478_amd import serve
+    b = seqgen.make_config(5, n_pairs=160, seed=3)
+    arrivals = np.cumsum(np.random.default_rng(31).exponential(1.0 / 3000.0, size=b.n_pairs))
+    kw = dict(slots=2, long_slots=1, max_batch_pairs=8, max_batch_bases=6000, long_batch_pairs=8,
+              long_batch_bases=40000, ring_factor=2)
+    res, lat, wall, nb = serve.serve_trace_native(b, arrivals, **kw)
+    _say(f"native: {b.n_pairs} requests in {nb} batches, {wall * 1e3:.1f} ms")
+    assert nb > 3 and np.all(lat > 0)
+    want, _ = oracle_align(b)
+    assert_same(res, want, b, "native served")
+    res_py, _, _, _ = serve.serve_trace(b, arrivals, **kw)
+    assert np.array_equal(res, res_py)
+    # one by one through submit/poll, eager steps
+    srv = serve.NativeServer(b.scoring, b.w, b.zdrop, 0, graphs=False, **kw)
+    lib = ga.load_library()
+    for k in range(20):
+        t, q = b.target(k), b.query(k)
+        assert lib.ga_server_submit(srv._h, k, t, len(t), q, len(q), -1.0) == ga.GA_OK
+    tags = np.zeros(64, dtype=np.int64)
+    out = np.zeros((64, 7), dtype=np.int32)
+    got = {}
+    for _ in range(40000):
+        nd = lib.ga_server_poll(srv._h, tags.ctypes.data, out.ctypes.data, None, 64)
+        assert nd >= 0
+        for i in range(nd):
+            got[int(tags[i])] = out[i].copy()
+        if len(got) == 20:
+            break
+        time.sleep(0.0005)
+    assert lib.ga_server_pending(srv._h) == 0
+    assert np.array_equal(np.array([got[k] for k in range(20)]), want[:20])
+    huge = b"A" * 200000
+    assert lib.ga_server_submit(srv._h, 99, huge, len(huge), b"A", 1, -1.0) == ga.GA_EUNSUPPORTED
+    srv.close()
