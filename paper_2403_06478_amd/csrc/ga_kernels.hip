@@ -919,31 +919,40 @@ __device__ __forceinline__ int window_base(const Geo &g, int slide, int base, in
 
 // Move the window one lane: down (dir < 0: lane l takes lane l-1's slots,
 // lane 0 starts at -inf) or up (lane l takes lane l+1's, lane 63 at -inf).
+// Each state array goes through LDS: row l+1 of `rows` takes lane l's K
+// slots, then every lane reads the row of its neighbour; rows 0 and 65 hold
+// -inf for the lane with no neighbour on that side. Staging costs no
+// registers beyond the state, and the rows are reused array after array.
 template <int K>
-__device__ __forceinline__ void shift_lanes(PairState<K> &st, int dir) {
-    if (dir < 0) {
+__device__ __forceinline__ void shift_array(typename PairState<K>::VecK &a, int *rows, int lane, int dir) {
+    int4 *own = reinterpret_cast<int4 *>(rows + (lane + 1) * K);
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-            st.A[s] = dpp_from_lower_lane(NEG, st.A[s]);
-            st.E[s] = dpp_from_lower_lane(NEG, st.E[s]);
-            st.X[s] = dpp_from_lower_lane(NEG, st.X[s]);
-            st.F[s] = dpp_from_lower_lane(NEG, st.F[s]);
-            st.Y[s] = dpp_from_lower_lane(NEG, st.Y[s]);
-        }
-    } else {
+    for (int q = 0; q < K / 4; ++q) own[q] = make_int4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+    __syncthreads();  // every row is staged before any lane reads its neighbour's
+    const int4 *from = reinterpret_cast<const int4 *>(rows + (lane + 1 + dir) * K);
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-            st.A[s] = dpp_from_upper_lane(NEG, st.A[s]);
-            st.E[s] = dpp_from_upper_lane(NEG, st.E[s]);
-            st.X[s] = dpp_from_upper_lane(NEG, st.X[s]);
-            st.F[s] = dpp_from_upper_lane(NEG, st.F[s]);
-            st.Y[s] = dpp_from_upper_lane(NEG, st.Y[s]);
-        }
+    for (int q = 0; q < K / 4; ++q) {
+        const int4 v = from[q];
+        a[4 * q] = v.x;
+        a[4 * q + 1] = v.y;
+        a[4 * q + 2] = v.z;
+        a[4 * q + 3] = v.w;
     }
+    __syncthreads();  // every lane has read before the next array is staged
+}
+
+template <int K>
+__device__ __forceinline__ void shift_lanes(PairState<K> &st, int *rows, int lane, int dir) {
+    static_assert(K % 4 == 0, "rows are staged 16 bytes at a time");
+    shift_array<K>(st.A, rows, lane, dir);
+    shift_array<K>(st.E, rows, lane, dir);
+    shift_array<K>(st.X, rows, lane, dir);
+    shift_array<K>(st.F, rows, lane, dir);
+    shift_array<K>(st.Y, rows, lane, dir);
 }
 
 template <int K, int NW, bool SL>
-__device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, NW> &S) {
+__device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, NW> &S, int *rows) {
     Geo g;
     g.n = P.t_len[p];
     g.m = P.q_len[p];
@@ -1022,7 +1031,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
             // move the window to this block's base, one lane at a time
             const int dir = base_next < g.a0w ? -1 : 1;
             const int lanes = (base_next - g.a0w) * dir / K;  // whole lanes by construction
-            for (int k = 0; k < lanes && k < WAVE; ++k) shift_lanes<K>(st, dir);
+            for (int k = 0; k < lanes && k < WAVE; ++k) shift_lanes<K>(st, rows, lane, dir);
             g.a0w = base_next;
             place_wall();
         }
@@ -1055,13 +1064,13 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     // (several waves: the wave that ended the sweep has written the result)
 }
 
-// Waves per SIMD each kernel is compiled for (register budget; a sliding
-// window needs room for the lane shifts). The one-wave K=32 kernel needs
-// more than the 256 registers two waves per SIMD leave it: at one wave per
-// SIMD its excess lives in accumulation registers instead of scratch memory.
+// Waves per SIMD each kernel is compiled for (register budget). The one-wave
+// K=32 kernel needs more than the 256 registers two waves per SIMD leave it:
+// at one wave per SIMD its excess lives in accumulation registers instead of
+// scratch memory.
 template <int K, int NW, bool SL>
 struct Occ {
-    static constexpr int value = K <= 8 ? 4 : (K <= 16 && !SL ? 3 : (K == 32 && NW == 1 ? 1 : 2));
+    static constexpr int value = K <= 8 ? 4 : (K <= 16 ? 3 : (K == 32 && NW == 1 ? 1 : 2));
 };
 
 // Each workgroup of NW waves takes pairs of its group from the list through
@@ -1070,8 +1079,17 @@ struct Occ {
 // (the bucketed schedule).
 template <int K, int NW, bool SL>
 __global__ __launch_bounds__(WAVE * NW, (Occ<K, NW, SL>::value)) void ga_dp_kernel(DpArgs P) {
+    static_assert(!SL || NW == 1, "a sliding window runs on one wave");
     __shared__ PairLds<K, NW> S;
+    // lane-shift staging of a sliding window: -inf rows on both sides
+    __shared__ __align__(16) int rows[SL ? (WAVE + 2) * K : 4];
     const int lane = threadIdx.x & (WAVE - 1);
+    if constexpr (SL) {
+        if (lane < K) {
+            rows[lane] = NEG;
+            rows[(WAVE + 1) * K + lane] = NEG;
+        }
+    }
     const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int count = P.counters[CNT_COUNT + P.group];
     const int32_t *list = P.list + P.counters[CNT_START + P.group];
@@ -1088,7 +1106,7 @@ __global__ __launch_bounds__(WAVE * NW, (Occ<K, NW, SL>::value)) void ga_dp_kern
         }
         if (idx >= count) break;
         const int p = list[idx];
-        align_pair<K, NW, SL>(P, p, lane, wv, S);
+        align_pair<K, NW, SL>(P, p, lane, wv, S, rows);
     }
 }
 
