@@ -15,7 +15,10 @@ pair planning and the anti-diagonal sweep with z-drop for every pair. Inputs
 are packed and resident in HBM before the timed region starts.
 
 Prints one JSON line: GCUPS = algorithmic in-band cells up to each pair's
-termination anti-diagonal, per second.
+termination anti-diagonal, per second. The line also gives the median device
+time of one step and, measured after the timed steps and not part of
+`value`, the end-to-end time from host ASCII (upload, packing, alignment,
+results back to the host).
 """
 
 from __future__ import annotations
@@ -43,6 +46,7 @@ WORKLOADS = {
                  "seed 0"),
 }
 
+E2E_RUNS = 3                # end-to-end repetitions after the timed steps (median reported)
 OPS_PER_CELL = 16           # int32 VALU lane-ops per cell (the roofline convention)
 PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # int32 lane-ops/s: CUs x SIMDs x lanes x clock
 DOMINANT_KERNEL_SRC = os.path.join(ROOT, "paper_2403_06478_amd", "csrc", "ga_kernels.hip")
@@ -93,10 +97,17 @@ def cpu_baseline(batch, n_sample: int):
     t0 = time.perf_counter()
     _, cells = oracle.align_batch(sub, nthreads=cores)
     dt = time.perf_counter() - t0
+    # one thread on a sixteenth of the sample (about as long again)
+    one = sub.subset(np.arange(max(1, sub.n_pairs // 16)))
+    t0 = time.perf_counter()
+    _, cells1 = oracle.align_batch(one, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(float(cells.sum()) / dt / 1e9, 4), "unit": "GCUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"first {sub.n_pairs} pairs of the benchmark batch "
-                      f"({int(cells.sum())} cells, {dt:.1f} s)"}
+                      f"({int(cells.sum())} cells, {dt:.1f} s)",
+            "one_core": {"value": round(float(cells1.sum()) / dt1 / 1e9, 4),
+                         "sample": f"first {one.n_pairs} pairs ({int(cells1.sum())} cells, {dt1:.1f} s)"}}
 
 
 def main():
@@ -158,11 +169,15 @@ def main():
 
     ctx.set_timing(True)
     stage_ms = []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
+        ev[k][0].record(stream)
         ga.ga_align_batch(ctx, packed, batch.scoring, batch.w, batch.zdrop, out=out, stream=stream)
+        ev[k][1].record(stream)
         stage_ms.append(ctx.timing())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -170,7 +185,8 @@ def main():
     ctx.check()
     elapsed = t1 - t0
     ms_per_step = elapsed / args.steps * 1e3
-    log(f"{ms_per_step:.2f} ms per step")
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    log(f"{ms_per_step:.2f} ms per step (device time per step: median {np.median(step_ms):.2f} ms)")
 
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
@@ -182,12 +198,29 @@ def main():
         del src, dst
 
     res = out.cpu().numpy()
+
+    # End to end, outside the timed steps: host ASCII uploaded from pageable
+    # memory, packed on the device, aligned, results copied back to the host.
+    e2e_ms = []
+    for _ in range(E2E_RUNS):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        pk = ga.pack_batch(ctx, batch, stream)
+        host = ga.ga_align_batch(ctx, pk, batch.scoring, batch.w, batch.zdrop, stream=stream).cpu().numpy()
+        e2e_ms.append((time.perf_counter() - ta) * 1e3)
+        del pk
+        if not np.array_equal(host, res):
+            raise RuntimeError("end-to-end run gave results different from the timed steps")
+    ctx.check()
+    log(f"end to end (upload, pack, align, results to host): median {np.median(e2e_ms):.2f} ms")
+
     t_len, q_len = batch.t_len, batch.q_len
     cells = ga.count_cells(t_len, q_len, batch.w, res)
     # the class each pair ran in (this context's autotuned order)
     cls = np.array([ctx.pair_class(int(n), int(m), batch.w) for n, m in zip(t_len, q_len)])
     total_cells = int(cells.sum())
     gcups = total_cells / (ms_per_step / 1e3) / 1e9
+    e2e_ms_med = float(np.median(e2e_ms))
     pairs_per_s = batch.n_pairs / (ms_per_step / 1e3)
 
     stage = np.array(stage_ms)  # [steps, 1 + classes]
@@ -235,6 +268,11 @@ def main():
                    "pairs": batch.n_pairs, "w": batch.w, "Z": batch.zdrop,
                    "cells": total_cells, "zdropped": int(res[:, 6].sum())},
         "pairs_per_s": round(pairs_per_s, 1),
+        "step_ms_median": round(float(np.median(step_ms)), 3),
+        "end_to_end": {"ms_median": round(e2e_ms_med, 3), "runs": E2E_RUNS,
+                       "gcups": round(total_cells / (e2e_ms_med / 1e3) / 1e9, 3),
+                       "pairs_per_s": round(batch.n_pairs / (e2e_ms_med / 1e3), 1),
+                       "includes": "host ASCII upload (pageable), packing kernel, alignment, results to host"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
