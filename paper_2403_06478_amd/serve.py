@@ -400,20 +400,24 @@ class NativeServer:
                                          ctypes.byref(cfg)), "ga_server_create")
         self._h = h
 
-    def replay(self, batch, arrivals: np.ndarray):
-        """Serve ``batch``'s pairs arriving at ``arrivals`` (seconds after the
-        start): (results [n, 7], latencies in seconds, wall seconds)."""
-        n = batch.n_pairs
+    def replay(self, batch, arrivals: np.ndarray, pairs=None):
+        """Serve requests arriving at ``arrivals`` (seconds after the start);
+        request k is pair ``pairs[k]`` of ``batch`` (pair k without
+        ``pairs``): (results [n, 7], latencies in seconds, wall seconds)."""
         arr = np.ascontiguousarray(arrivals, dtype=np.float64)
+        n = int(arr.shape[0])
+        sel = np.arange(batch.n_pairs) if pairs is None else np.asarray(pairs, dtype=np.int64)
+        if sel.shape[0] != n:
+            raise ValueError("one arrival time per request")
         res = np.zeros((n, 7), dtype=np.int32)
         lat = np.zeros(n, dtype=np.float64)
         wall = ctypes.c_double(0.0)
         t_seq = np.ascontiguousarray(batch.t_seq, dtype=np.uint8)
         q_seq = np.ascontiguousarray(batch.q_seq, dtype=np.uint8)
-        t_off = np.ascontiguousarray(batch.t_off, dtype=np.int64)
-        q_off = np.ascontiguousarray(batch.q_off, dtype=np.int64)
-        t_len = np.ascontiguousarray(batch.t_len, dtype=np.int32)
-        q_len = np.ascontiguousarray(batch.q_len, dtype=np.int32)
+        t_off = np.ascontiguousarray(np.asarray(batch.t_off)[sel], dtype=np.int64)
+        q_off = np.ascontiguousarray(np.asarray(batch.q_off)[sel], dtype=np.int64)
+        t_len = np.ascontiguousarray(np.asarray(batch.t_len)[sel], dtype=np.int32)
+        q_len = np.ascontiguousarray(np.asarray(batch.q_len)[sel], dtype=np.int32)
         _check(self.lib.ga_server_replay(self._h, t_seq.ctypes.data, t_off.ctypes.data, t_len.ctypes.data,
                                          q_seq.ctypes.data, q_off.ctypes.data, q_len.ctypes.data, arr.ctypes.data,
                                          n, res.ctypes.data, lat.ctypes.data, ctypes.byref(wall)),
@@ -436,20 +440,24 @@ class NativeServer:
             pass
 
 
-def serve_trace_native(batch, arrivals: np.ndarray, device: int = 0, **server_args):
+def serve_trace_native(batch, arrivals: np.ndarray, device: int = 0, pairs=None, **server_args):
     """As serve_trace, with the native server."""
     srv = NativeServer(batch.scoring, batch.w, batch.zdrop, device, **server_args)
-    res, lat, wall = srv.replay(batch, arrivals)
+    res, lat, wall = srv.replay(batch, arrivals, pairs)
     nb = srv.batches
     srv.close()
     return res, lat, wall, nb
 
 
-def serve_trace(batch, arrivals: np.ndarray, device: int = 0, **server_args):
-    """Replay a request trace: request k (pair k of ``batch``) arrives at
-    ``arrivals[k]`` seconds after the start. Returns (results [n, 7],
-    latencies in seconds, wall seconds, batches launched)."""
-    n = batch.n_pairs
+def serve_trace(batch, arrivals: np.ndarray, device: int = 0, pairs=None, **server_args):
+    """Replay a request trace: request k (pair ``pairs[k]`` of ``batch``,
+    pair k without ``pairs``) arrives at ``arrivals[k]`` seconds after the
+    start. Returns (results [n, 7], latencies in seconds, wall seconds,
+    batches launched)."""
+    n = int(np.asarray(arrivals).shape[0])
+    sel = np.arange(batch.n_pairs) if pairs is None else np.asarray(pairs, dtype=np.int64)
+    if sel.shape[0] != n:
+        raise ValueError("one arrival time per request")
     srv = Server(batch.scoring, batch.w, batch.zdrop, device, **server_args)
     results = np.zeros((n, 7), dtype=np.int32)
     t_arr = np.zeros(n)
@@ -461,7 +469,7 @@ def serve_trace(batch, arrivals: np.ndarray, device: int = 0, **server_args):
         now = time.perf_counter() - t0
         while nxt < n and arrivals[nxt] <= now:
             t_arr[nxt] = t0 + arrivals[nxt]
-            srv.submit(nxt, batch.target(nxt), batch.query(nxt), t_arr[nxt])
+            srv.submit(nxt, batch.target(int(sel[nxt])), batch.query(int(sel[nxt])), t_arr[nxt])
             nxt += 1
         for rid, row, t in srv.step():
             results[rid] = row
@@ -514,6 +522,9 @@ def main(argv=None):
     ap.add_argument("--python", action="store_true", help="drive the slots from the Python loop (Server) "
                     "instead of the native server")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--duration", type=float, default=None,
+                    help="seconds of arrivals per rate, cycling over the request pool (default: "
+                         "each rate serves the pool once)")
     args = ap.parse_args(argv)
     torch = _torch()
     torch.cuda.set_device(0)
@@ -522,7 +533,8 @@ def main(argv=None):
               max_batch_bases=args.max_batch_bases, long_batch_pairs=args.long_batch_pairs,
               long_batch_bases=args.long_batch_bases, graphs=not args.no_graphs)
     res_off, dt_off = offline(batch)
-    cells = int(count_cells(batch.t_len, batch.q_len, batch.w, res_off).sum())
+    cells_pool = count_cells(batch.t_len, batch.q_len, batch.w, res_off)
+    cells = int(cells_pool.sum())
     sys.stderr.write(f"[serve] offline: {batch.n_pairs} requests as one batch in {dt_off * 1e3:.1f} ms "
                      f"({batch.n_pairs / dt_off:.0f} req/s, {cells / dt_off / 1e9:.1f} GCUPS)\n")
     # the server's own capacity: every request waiting at the start
@@ -533,23 +545,28 @@ def main(argv=None):
                      f"{cells / wall_sat / 1e9:.1f} GCUPS\n")
     if not np.array_equal(res_sat, res_off):
         raise SystemExit("served results differ from the offline batch")
-    long_ = batch.t_len + batch.q_len > 8000
+    long_pool = batch.t_len + batch.q_len > 8000
     for frac in args.rates:
         qps = frac * capacity
         rng = np.random.default_rng([5, args.seed, 1])
-        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=batch.n_pairs))
-        res, lat, wall, nb = run(batch, arrivals, **kw)
-        same = bool(np.array_equal(res, res_off))
+        n_req = batch.n_pairs if args.duration is None else max(1, int(np.ceil(qps * args.duration)))
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n_req))
+        pairs = np.arange(n_req) % batch.n_pairs  # request k asks for pool pair k mod pool size
+        res, lat, wall, nb = run(batch, arrivals, pairs=pairs, **kw)
+        same = bool(np.array_equal(res, res_off[pairs]))
+        long_ = long_pool[pairs]
+        req_cells = int(cells_pool[pairs].sum())
         line = {
             "metric": "serving latency", "unit": "ms", "qps": round(qps, 1), "rate_of_capacity": frac,
-            "capacity_req_per_s": round(capacity, 1), "requests": batch.n_pairs,
+            "capacity_req_per_s": round(capacity, 1), "requests": n_req, "pool": batch.n_pairs,
+            "served_req_per_s": round(n_req / wall, 1),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
             "p50_short_ms": round(float(np.percentile(lat[~long_], 50)) * 1e3, 3),
             "p99_short_ms": round(float(np.percentile(lat[~long_], 99)) * 1e3, 3),
             "p50_long_ms": round(float(np.percentile(lat[long_], 50)) * 1e3, 3) if long_.any() else None,
             "p99_long_ms": round(float(np.percentile(lat[long_], 99)) * 1e3, 3) if long_.any() else None,
-            "gcups": round(cells / wall / 1e9, 3), "offline_gcups": round(cells / dt_off / 1e9, 3),
+            "gcups": round(req_cells / wall / 1e9, 3), "offline_gcups": round(cells / dt_off / 1e9, 3),
             "saturated_gcups": round(cells / wall_sat / 1e9, 3),
             "batches": nb, "wall_s": round(wall, 3), "same_as_offline": same, "graphs": not args.no_graphs,
             "host_loop": "python" if args.python else "native",

@@ -621,6 +621,13 @@ def test_native_server():
     assert_same(res, want, b, "native served")
     res_py, _, _, _ = serve.serve_trace(b, arrivals, **kw)
     assert np.array_equal(res, res_py)
+    # a trace cycling over the pool (request k asks for pair k mod 160), so
+    # the rings wrap many times: every request gets its pair's result
+    pairs = np.arange(3 * b.n_pairs) % b.n_pairs
+    arr3 = np.cumsum(np.random.default_rng(32).exponential(1.0 / 6000.0, size=pairs.shape[0]))
+    res3, lat3, _, _ = serve.serve_trace_native(b, arr3, pairs=pairs, **kw)
+    assert np.all(lat3 > 0)
+    assert np.array_equal(res3, want[pairs])
     # one by one through submit/poll, eager steps
     srv = serve.NativeServer(b.scoring, b.w, b.zdrop, 0, graphs=False, **kw)
     lib = ga.load_library()
