@@ -1452,9 +1452,14 @@ constexpr int NEVENTS = 2 + 2 * NGROUP;
 // The persistent launches run on up to three streams at once (the caller's
 // and two of the context's), joined back into the caller's stream; the
 // lane of each class is fixed so the heavy classes of a mixed batch (K=24,
-// sliding K=8, K=4, K=16) land on different streams.
+// sliding K=8, K=4, K=16) land on different streams. The multi-wave
+// classes launch first, so their launches, usually empty, end at once
+// instead of waiting behind a full grid of another class for the resources
+// of their wide workgroups; then the one-wave classes in class order.
 constexpr int MAX_LANES = 3;
 constexpr int LANE_OF[NCLASS] = {0, 2, 1, 0, 1, 1, 2, 1, 0, 2, 0};
+constexpr int FIRST_MULTIWAVE = 7;  // classes 7 .. NCLASS-1 run several waves per pair
+static_assert(class_nw(FIRST_MULTIWAVE - 1) == 1 && class_nw(FIRST_MULTIWAVE) > 1, "multi-wave classes last");
 
 struct ga_context {
     int device;
@@ -2062,7 +2067,11 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
                 lane_s[k] = ctx->side[k - 1];
             }
         }
-        for (int c = 0; c < NCLASS; ++c) {
+        for (int k = 0; k < NCLASS; ++k) {
+            // the multi-wave classes first (widest first), then the others
+            // in class order
+            const int nmw = NCLASS - FIRST_MULTIWAVE;
+            const int c = k < nmw ? NCLASS - 1 - k : k - nmw;
             if (!((ctx->class_mask >> c) & 1u)) continue;
             const int64_t want = (int64_t)ctx->num_cu * ctx->blocks_per_cu[c];
             const int grid = (int)(np < want ? np : want);

@@ -130,6 +130,38 @@ def test_cfg2_full_size_sampled():
     assert np.all(got[:, 3] <= got[:, 0])  # the end is never above the maximum
 
 
+def test_cfg3_full_size_sampled():
+    """The heavy-tailed 1M-pair workload in one call (every class, the
+    streams overlapped, as timed): random pairs, the longest pairs, pairs
+    that dropped and short-by-long pairs against the oracle; every pair
+    against cheap properties."""
+    import paper_2403_06478_amd as ga
+    b = seqgen.make_config(3)
+    _say(f"cfg3 full: {b.n_pairs} pairs")
+    got = gpu_align(b)
+    rng = np.random.default_rng(3)
+    n, m = b.t_len.astype(np.int64), b.q_len.astype(np.int64)
+    longest = np.argsort(-(n + m), kind="stable")[:4]
+    dropped = np.nonzero(got[:, 6] == 1)[0]
+    lopsided = np.nonzero(np.abs(m - n) > 2 * b.w)[0]
+    idx = np.unique(np.concatenate([
+        rng.choice(b.n_pairs, size=160, replace=False), longest,
+        rng.choice(dropped, size=min(16, dropped.size), replace=False),
+        rng.choice(lopsided, size=min(24, lopsided.size), replace=False)]))
+    classes = {ga.class_name(ga.ga_pair_class(int(n[p]), int(m[p]), b.w)) for p in idx}
+    _say(f"cfg3 full: {idx.size} sampled pairs in classes {sorted(classes)}")
+    assert any("sliding" in c for c in classes)
+    sub = b.subset(idx)
+    want, _ = oracle_align(sub)
+    assert_same(got[idx], want, sub, "cfg3 full sampled")
+    assert np.all(got[:, 0] >= 0)
+    assert np.all((got[:, 1] >= -1) & (got[:, 1] < n) & (got[:, 2] >= -1) & (got[:, 2] < m))
+    assert np.all((got[:, 4] >= 0) & (got[:, 4] < n) & (got[:, 5] >= 0) & (got[:, 5] < m))
+    assert np.all(np.abs(got[:, 4] - got[:, 5]) <= b.w)
+    assert set(np.unique(got[:, 6]).tolist()) <= {0, 1}
+    assert np.all(got[:, 3] <= got[:, 0])
+
+
 def test_deterministic_and_order_independent():
     b = seqgen.make_config(2, n_pairs=300)
     x = gpu_align(b)
