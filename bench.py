@@ -36,12 +36,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # name: (seqgen workload id, description)
-    "ont": (2, "ONT-like batch: 100k pairs, target LogNormal(median 2 kb, sigma 0.8) capped at 20 kb, "
+    # name: (seqgen workload, description)
+    "ont": ("ont", "ONT-like batch: 100k pairs, target LogNormal(median 2 kb, sigma 0.8) capped at 20 kb, "
                "10% errors 1:1:1, 0.1% N scored -1, a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, seed 0"),
-    "longread": (4, "HiFi-like long reads: 20k pairs, target U{10000..25000}, 1% errors 1:1:1 plus 1-3 "
+    "longread": ("longread", "HiFi-like long reads: 20k pairs, target U{10000..25000}, 1% errors 1:1:1 plus 1-3 "
                     "indels of U{50..500} bp, a=2 b=4 q=4 e=2 q2=24 e2=1, w=2000, Z=5000, seed 0"),
-    "mixed": (3, "heavy-tailed mix: 1M pairs, target min(50000, 50 U^(-1/1.5)), 8% errors 1:1:1, 20% of "
+    "mixed": ("mix", "heavy-tailed mix: 1M pairs, target min(50000, 50 U^(-1/1.5)), 8% errors 1:1:1, 20% of "
                  "queries with a U{2000..5000} random insert, a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, "
                  "seed 0"),
 }
@@ -147,7 +147,7 @@ def main():
     torch.cuda.set_device(0)
     wid, wdesc = WORKLOADS[args.workload]
     log(f"generating workload '{args.workload}'")
-    batch = seqgen.make_config(wid, n_pairs=args.pairs)
+    batch = seqgen.make_workload(wid, n_pairs=args.pairs)
     ctx = ga.Context(0)
     ctx.set_schedule(args.schedule)
     class_cost = None

@@ -23,7 +23,7 @@ Every step of the alignment runs in the HIP library; this module only
 schedules batches and places bytes.
 
 ``python -m paper_2403_06478_amd.serve`` runs the serving benchmark: the
-request mix of ``seqgen`` workload 5 with Poisson arrivals at given
+request mix of the ``seqgen`` workload ``serving`` with Poisson arrivals at given
 fractions of the offline capacity, one JSON line per rate.
 """
 
@@ -528,7 +528,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     torch = _torch()
     torch.cuda.set_device(0)
-    batch = seqgen.make_config(5, n_pairs=args.requests, seed=args.seed)
+    batch = seqgen.make_workload("serving", n_pairs=args.requests, seed=args.seed)
     kw = dict(slots=args.slots, long_slots=args.long_slots, max_batch_pairs=args.max_batch_pairs,
               max_batch_bases=args.max_batch_bases, long_batch_pairs=args.long_batch_pairs,
               long_batch_bases=args.long_batch_bases, graphs=not args.no_graphs)
@@ -570,7 +570,7 @@ def main(argv=None):
             "saturated_gcups": round(cells / wall_sat / 1e9, 3),
             "batches": nb, "wall_s": round(wall, 3), "same_as_offline": same, "graphs": not args.no_graphs,
             "host_loop": "python" if args.python else "native",
-            "workload": "seqgen workload 5: 95% pairs of 100-1000 bp (5% errors), 5% of 10-25 kb "
+            "workload": "seqgen serving workload: 95% pairs of 100-1000 bp (5% errors), 5% of 10-25 kb "
                         "(1% errors + indels), w=500, Z=400, Poisson arrivals",
         }
         print(json.dumps(line), flush=True)

@@ -11,23 +11,26 @@ in for it. Every sequence is ASCII (``A C G T`` and ``N``), concatenated into
 one ``uint8`` buffer per side with ``int64`` start offsets and ``int32``
 lengths, so the same bytes feed the oracle and the device packer.
 
-Workload recipes (target = reference, query = mutated target):
+Workload recipes (target = reference, query = mutated target), by name
+(``make_workload(name)``; the number in brackets seeds the generator):
 
-* ``cfg1``  500 pairs, target length U{100..1000}, 5% errors (subst:ins:del
-  2:1:1), no N; band 500, z-drop 400.
-* ``cfg2``  100k ONT-like pairs, target length clip(round(LogNormal(ln 2000,
-  0.8)), 1, 20000), 10% errors (1:1:1), then every base of both sequences
-  becomes N with probability 0.001; band 751, z-drop 400.
-* ``cfg3``  1M pairs, target length min(50000, floor(50 * U**(-1/1.5)))
+* ``uniform`` [1]  500 pairs, target length U{100..1000}, 5% errors
+  (subst:ins:del 2:1:1), no N; band 500, z-drop 400.
+* ``ont`` [2]  100k ONT-like pairs, target length clip(round(LogNormal(ln
+  2000, 0.8)), 1, 20000), 10% errors (1:1:1), then every base of both
+  sequences becomes N with probability 0.001; band 751, z-drop 400.
+* ``mix`` [3]  1M pairs, target length min(50000, floor(50 * U**(-1/1.5)))
   (Pareto tail, alpha 1.5), 8% errors (1:1:1); 20% of the pairs get an
   unrelated U{2000..5000} random segment inserted into the query at a uniform
   position; band 751, z-drop 400.
-* ``cfg4``  20k HiFi-like pairs, target length U{10000..25000}, 1% errors
-  (1:1:1) plus U{1,2,3} long indels of U{50..500} bases each (insertion of
-  random bases or deletion, probability 1/2 each); band 2000, z-drop 5000.
-* ``cfg5``  serving requests, one pair each, in request order: with
-  probability 0.95 drawn as in cfg1, else as in cfg4; band 500, z-drop 400
-  for every request. Arrival times are drawn by the serving benchmark.
+* ``longread`` [4]  20k HiFi-like pairs, target length U{10000..25000}, 1%
+  errors (1:1:1) plus U{1,2,3} long indels of U{50..500} bases each
+  (insertion of random bases or deletion, probability 1/2 each); band 2000,
+  z-drop 5000.
+* ``serving`` [5]  serving requests, one pair each, in request order: with
+  probability 0.95 drawn as in ``uniform``, else as in ``longread``; band
+  500, z-drop 400 for every request. Arrival times are drawn by the serving
+  benchmark.
 
 ``long_ratio`` (the synthetic study of Section 5.6, Fig. 12): a given
 fraction of 4096-base targets among 128-base ones, 5% errors (1:1:1).
@@ -35,7 +38,7 @@ fraction of 4096-base targets among 128-base ones, 5% errors (1:1:1).
 Point errors: each target base independently is an error with the stated
 rate; a substitution draws one of the three other bases uniformly, an
 insertion emits a random base after the original, a deletion drops the base.
-Every config is drawn from ``numpy.random.default_rng([config_id, seed])``.
+Every workload is drawn from ``numpy.random.default_rng([number, seed])``.
 """
 
 from __future__ import annotations
@@ -196,18 +199,24 @@ def _finish(t_seq, t_lens, q_seq, q_lens, w, zdrop, name):
                      dict(SCORING), int(w), int(zdrop), name)
 
 
-CONFIG_PAIRS = {1: 500, 2: 100_000, 3: 1_000_000, 4: 20_000, 5: 20_000}
-CONFIG_BAND = {1: (500, 400), 2: (751, 400), 3: (751, 400), 4: (2000, 5000), 5: (500, 400)}
+# name -> (seed number, pairs, band, z-drop)
+WORKLOADS = {
+    "uniform": (1, 500, 500, 400),
+    "ont": (2, 100_000, 751, 400),
+    "mix": (3, 1_000_000, 751, 400),
+    "longread": (4, 20_000, 2000, 5000),
+    "serving": (5, 20_000, 500, 400),
+}
 
 
-def _cfg1_pairs(rng, P):
+def _uniform_pairs(rng, P):
     tl = rng.integers(100, 1001, size=P)
     t = _random_bases(rng, int(tl.sum()))
     q, ql = _mutate(rng, t, tl, 0.05, (2, 1, 1))
     return t, tl, q, ql
 
 
-def _cfg4_pairs(rng, P):
+def _long_read_pairs(rng, P):
     tl = rng.integers(10000, 25001, size=P)
     t = _random_bases(rng, int(tl.sum()))
     q, ql = _mutate(rng, t, tl, 0.01, (1, 1, 1))
@@ -243,35 +252,36 @@ def _interleave(parts, which):
     return t_all, np.array(tl_out), q_all, np.array(ql_out)
 
 
-def make_config(config_id: int, n_pairs: Optional[int] = None, seed: int = 0) -> PairBatch:
-    """Draw workload ``config_id`` (1..5). ``n_pairs`` truncates the draw to a
-    prefix-sized batch with the same distribution (a smaller sample)."""
-    if config_id not in CONFIG_PAIRS:
-        raise ValueError(f"unknown config {config_id}")
-    rng = np.random.default_rng([config_id, seed])
-    P = CONFIG_PAIRS[config_id] if n_pairs is None else int(n_pairs)
-    w, zdrop = CONFIG_BAND[config_id]
-    name = f"cfg{config_id}" + ("" if n_pairs is None else f"[{P}]")
-    if config_id == 1:
-        t, tl, q, ql = _cfg1_pairs(rng, P)
-        return _finish(t, tl, q, ql, w, zdrop, name)
-    if config_id == 5:
-        # serving requests: 95% drawn like cfg1, 5% cfg4-sized, in a random
+def make_workload(name: str, n_pairs: Optional[int] = None, seed: int = 0) -> PairBatch:
+    """Draw the workload ``name`` (a key of ``WORKLOADS``). ``n_pairs``
+    truncates the draw to a prefix-sized batch with the same distribution (a
+    smaller sample)."""
+    if name not in WORKLOADS:
+        raise ValueError(f"unknown workload {name!r} (one of {sorted(WORKLOADS)})")
+    number, pairs, w, zdrop = WORKLOADS[name]
+    rng = np.random.default_rng([number, seed])
+    P = pairs if n_pairs is None else int(n_pairs)
+    label = name + ("" if n_pairs is None else f"[{P}]")
+    if name == "uniform":
+        t, tl, q, ql = _uniform_pairs(rng, P)
+        return _finish(t, tl, q, ql, w, zdrop, label)
+    if name == "serving":
+        # 95% drawn like the uniform pairs, 5% long-read-sized, in a random
         # request order; band 500 and z-drop 400 shared by every request
         is_long = rng.random(P) < 0.05
         n_long = int(is_long.sum())
-        short = _cfg1_pairs(rng, P - n_long)
-        long_ = _cfg4_pairs(rng, n_long)
+        short = _uniform_pairs(rng, P - n_long)
+        long_ = _long_read_pairs(rng, n_long)
         t, tl, q, ql = _interleave([short, long_], is_long.astype(np.int64))
-        return _finish(t, tl, q, ql, w, zdrop, name)
-    if config_id == 2:
+        return _finish(t, tl, q, ql, w, zdrop, label)
+    if name == "ont":
         tl = np.clip(np.round(rng.lognormal(np.log(2000.0), 0.8, size=P)), 1, 20000).astype(np.int64)
         t = _random_bases(rng, int(tl.sum()))
         q, ql = _mutate(rng, t, tl, 0.10, (1, 1, 1))
         t = _sprinkle_n(rng, t, 0.001)
         q = _sprinkle_n(rng, q, 0.001)
-        return _finish(t, tl, q, ql, w, zdrop, name)
-    if config_id == 3:
+        return _finish(t, tl, q, ql, w, zdrop, label)
+    if name == "mix":
         u = rng.random(P)
         u = np.maximum(u, np.finfo(np.float64).tiny)
         tl = np.minimum(50000, np.floor(50.0 * u ** (-1.0 / 1.5))).astype(np.int64)
@@ -279,10 +289,9 @@ def make_config(config_id: int, n_pairs: Optional[int] = None, seed: int = 0) ->
         q, ql = _mutate(rng, t, tl, 0.08, (1, 1, 1))
         which = rng.random(P) < 0.20
         q, ql = _splice(rng, q, ql, which, 2000, 5000, "ins")
-        return _finish(t, tl, q, ql, w, zdrop, name)
-    # config 4
-    t, tl, q, ql = _cfg4_pairs(rng, P)
-    return _finish(t, tl, q, ql, w, zdrop, name)
+        return _finish(t, tl, q, ql, w, zdrop, label)
+    t, tl, q, ql = _long_read_pairs(rng, P)  # longread
+    return _finish(t, tl, q, ql, w, zdrop, label)
 
 
 def long_ratio(n_pairs: int, frac_long: float, seed: int = 0, long_len: int = 4096,

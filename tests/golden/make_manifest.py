@@ -16,10 +16,10 @@ import seqgen  # noqa: E402
 
 
 def main():
-    lines = ["# config pairs bases sha256 (seqgen.make_config(config), seed 0)"]
-    for c in (1, 2, 3, 4, 5):
-        b = seqgen.make_config(c)
-        lines.append(f"{c} {b.n_pairs} {int(b.t_len.sum() + b.q_len.sum())} {b.digest()}")
+    lines = ["# workload pairs bases sha256 (seqgen.make_workload(workload), seed 0)"]
+    for name in seqgen.WORKLOADS:
+        b = seqgen.make_workload(name)
+        lines.append(f"{name} {b.n_pairs} {int(b.t_len.sum() + b.q_len.sum())} {b.digest()}")
     with open(os.path.join(HERE, "seqgen_manifest.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -21,11 +21,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def test_cfg1_full():
-    b = seqgen.make_config(1)
-    _say(f"cfg1 full: {b.n_pairs} pairs w={b.w} Z={b.zdrop}")
+def test_uniform_500_pairs_full():
+    b = seqgen.make_workload("uniform")
+    _say(f"uniform 500 pairs: {b.n_pairs} pairs w={b.w} Z={b.zdrop}")
     want, _ = oracle_align(b)
-    assert_same(gpu_align(b), want, b, "cfg1")
+    assert_same(gpu_align(b), want, b, "uniform")
 
 
 def test_golden_closed_forms_on_gpu():
@@ -87,38 +87,38 @@ def test_band_wider_than_sequences_and_lopsided():
         assert_same(gpu_align(b), want, b, f"lopsided w={w}")
 
 
-def test_cfg2_sample():
-    b = seqgen.make_config(2, n_pairs=400)
-    _say(f"cfg2 sample: {b.n_pairs} pairs")
+def test_ont_like_sample():
+    b = seqgen.make_workload("ont", n_pairs=400)
+    _say(f"ONT-like sample: {b.n_pairs} pairs")
     want, _ = oracle_align(b)
-    assert_same(gpu_align(b), want, b, "cfg2[400]")
+    assert_same(gpu_align(b), want, b, "ont[400]")
 
 
-def test_cfg3_sample():
-    full = seqgen.make_config(3, n_pairs=4000)
+def test_mix_sample():
+    full = seqgen.make_workload("mix", n_pairs=4000)
     # keep the oracle's work bounded: drop the rare >8 kb targets
     idx = np.nonzero(full.t_len <= 8000)[0][:1500]
     b = full.subset(idx)
-    _say(f"cfg3 sample: {b.n_pairs} pairs")
+    _say(f"mix sample: {b.n_pairs} pairs")
     want, _ = oracle_align(b)
     got = gpu_align(b)
-    assert_same(got, want, b, "cfg3 sample")
+    assert_same(got, want, b, "mix sample")
     # short targets cannot fall Z = 400 below their maximum, so only the
     # longer pairs with an inserted segment drop
     assert got[:, 6].sum() >= 1
 
 
-def test_cfg2_full_size_sampled():
+def test_ont_like_100k_full_size_sampled():
     """The bench workload at full size (100k pairs, one launch): sampled
     pairs against the oracle, every pair against cheap properties."""
-    b = seqgen.make_config(2)
-    _say(f"cfg2 full: {b.n_pairs} pairs")
+    b = seqgen.make_workload("ont")
+    _say(f"ONT-like full: {b.n_pairs} pairs")
     got = gpu_align(b)
     rng = np.random.default_rng(2)
     idx = np.sort(rng.choice(b.n_pairs, size=120, replace=False))
     sub = b.subset(idx)
     want, _ = oracle_align(sub)
-    assert_same(got[idx], want, sub, "cfg2 full sampled")
+    assert_same(got[idx], want, sub, "ont full sampled")
     # properties at every pair: G >= 0, positions inside the matrix, the end
     # on an anti-diagonal no later than the last cell, the flag binary
     n, m = b.t_len.astype(np.int64), b.q_len.astype(np.int64)
@@ -130,14 +130,14 @@ def test_cfg2_full_size_sampled():
     assert np.all(got[:, 3] <= got[:, 0])  # the end is never above the maximum
 
 
-def test_cfg3_full_size_sampled():
+def test_mix_1m_full_size_sampled():
     """The heavy-tailed 1M-pair workload in one call (every class, the
     streams overlapped, as timed): random pairs, the longest pairs, pairs
     that dropped and short-by-long pairs against the oracle; every pair
     against cheap properties."""
     import paper_2403_06478_amd as ga
-    b = seqgen.make_config(3)
-    _say(f"cfg3 full: {b.n_pairs} pairs")
+    b = seqgen.make_workload("mix")
+    _say(f"mix full: {b.n_pairs} pairs")
     got = gpu_align(b)
     rng = np.random.default_rng(3)
     n, m = b.t_len.astype(np.int64), b.q_len.astype(np.int64)
@@ -149,11 +149,11 @@ def test_cfg3_full_size_sampled():
         rng.choice(dropped, size=min(16, dropped.size), replace=False),
         rng.choice(lopsided, size=min(24, lopsided.size), replace=False)]))
     classes = {ga.class_name(ga.ga_pair_class(int(n[p]), int(m[p]), b.w)) for p in idx}
-    _say(f"cfg3 full: {idx.size} sampled pairs in classes {sorted(classes)}")
+    _say(f"mix full: {idx.size} sampled pairs in classes {sorted(classes)}")
     assert any("sliding" in c for c in classes)
     sub = b.subset(idx)
     want, _ = oracle_align(sub)
-    assert_same(got[idx], want, sub, "cfg3 full sampled")
+    assert_same(got[idx], want, sub, "mix full sampled")
     assert np.all(got[:, 0] >= 0)
     assert np.all((got[:, 1] >= -1) & (got[:, 1] < n) & (got[:, 2] >= -1) & (got[:, 2] < m))
     assert np.all((got[:, 4] >= 0) & (got[:, 4] < n) & (got[:, 5] >= 0) & (got[:, 5] < m))
@@ -163,7 +163,7 @@ def test_cfg3_full_size_sampled():
 
 
 def test_deterministic_and_order_independent():
-    b = seqgen.make_config(2, n_pairs=300)
+    b = seqgen.make_workload("ont", n_pairs=300)
     x = gpu_align(b)
     y = gpu_align(b)
     assert np.array_equal(x, y)
@@ -236,26 +236,26 @@ def test_multiwave_unbanded_and_drops():
             assert got[:, 6].sum() >= 1
 
 
-def test_cfg4_sample():
+def test_long_reads_sample():
     """The long-read workload (w=2000, Z=5000, 10-25 kb): a few whole pairs
     against the oracle."""
-    b = seqgen.make_config(4, n_pairs=6)
-    _say(f"cfg4 sample: {b.n_pairs} pairs, lengths {b.t_len.tolist()}")
+    b = seqgen.make_workload("longread", n_pairs=6)
+    _say(f"long-read sample: {b.n_pairs} pairs, lengths {b.t_len.tolist()}")
     want, _ = oracle_align(b)
-    assert_same(gpu_align(b), want, b, "cfg4[6]")
+    assert_same(gpu_align(b), want, b, "longread[6]")
 
 
-def test_cfg4_full_size_sampled():
+def test_long_reads_20k_full_size_sampled():
     """The whole 20k-pair long-read workload in one launch: sampled pairs
     against the oracle, every pair against cheap properties."""
-    b = seqgen.make_config(4)
-    _say(f"cfg4 full: {b.n_pairs} pairs")
+    b = seqgen.make_workload("longread")
+    _say(f"long-read full: {b.n_pairs} pairs")
     got = gpu_align(b)
     rng = np.random.default_rng(4)
     idx = np.sort(rng.choice(b.n_pairs, size=8, replace=False))
     sub = b.subset(idx)
     want, _ = oracle_align(sub)
-    assert_same(got[idx], want, sub, "cfg4 full sampled")
+    assert_same(got[idx], want, sub, "longread full sampled")
     n, m = b.t_len.astype(np.int64), b.q_len.astype(np.int64)
     assert np.all(got[:, 0] >= 0)
     assert np.all((got[:, 4] >= 0) & (got[:, 4] < n) & (got[:, 5] >= 0) & (got[:, 5] < m))
@@ -266,7 +266,7 @@ def test_cfg4_full_size_sampled():
 
 def test_cells_closed_form():
     import paper_2403_06478_amd as ga
-    b = seqgen.make_config(1, n_pairs=60)
+    b = seqgen.make_workload("uniform", n_pairs=60)
     got = gpu_align(b)
     _, cells = oracle_align(b)
     lib_cells = ga.count_cells(b.t_len, b.q_len, b.w, got)
@@ -389,7 +389,7 @@ def test_bucketed_schedule_same_results():
     import torch
 
     import paper_2403_06478_amd as ga
-    full = seqgen.make_config(3, n_pairs=3000)
+    full = seqgen.make_workload("mix", n_pairs=3000)
     idx = np.nonzero(full.t_len <= 6000)[0][:1200]
     b = full.subset(idx)
     ctx = ga.Context(0)
@@ -416,7 +416,7 @@ def test_serving_isolation():
     and the same request run alone."""
     import paper_2403_06478_amd as ga
     from paper_2403_06478_amd import serve
-    b = seqgen.make_config(5, n_pairs=160, seed=3)
+    b = seqgen.make_workload("serving", n_pairs=160, seed=3)
     arrivals = np.cumsum(np.random.default_rng(31).exponential(1.0 / 3000.0, size=b.n_pairs))
     # small rings (twice a batch) so requests wait for ring space and the
     # ring wraps around
@@ -610,7 +610,7 @@ def test_lanes_same_results():
     import torch
 
     import paper_2403_06478_amd as ga
-    full = seqgen.make_config(3, n_pairs=3000, seed=4)
+    full = seqgen.make_workload("mix", n_pairs=3000, seed=4)
     b = full.subset(np.nonzero(full.t_len <= 6000)[0][:1500])
     ctx = ga.Context(0)
     lib = ga.load_library()
@@ -642,7 +642,7 @@ def test_native_server():
 
     import paper_2403_06478_amd as ga
     from paper_2403_06478_amd import serve
-    b = seqgen.make_config(5, n_pairs=160, seed=3)
+    b = seqgen.make_workload("serving", n_pairs=160, seed=3)
     arrivals = np.cumsum(np.random.default_rng(31).exponential(1.0 / 3000.0, size=b.n_pairs))
     kw = dict(slots=2, long_slots=1, max_batch_pairs=8, max_batch_bases=6000, long_batch_pairs=8,
               long_batch_bases=40000, ring_factor=2)

@@ -15,14 +15,14 @@ def _entries():
     rows = []
     for line in open(MANIFEST):
         if line.strip() and not line.startswith("#"):
-            c, n, bases, digest = line.split()
-            rows.append((int(c), int(n), int(bases), digest))
+            name, n, bases, digest = line.split()
+            rows.append((name, int(n), int(bases), digest))
     return rows
 
 
-@pytest.mark.parametrize("config,n_pairs,bases,digest", _entries())
-def test_workload_matches_manifest(config, n_pairs, bases, digest):
-    b = seqgen.make_config(config)
+@pytest.mark.parametrize("workload,n_pairs,bases,digest", _entries())
+def test_workload_matches_manifest(workload, n_pairs, bases, digest):
+    b = seqgen.make_workload(workload)
     assert b.n_pairs == n_pairs
     assert int(b.t_len.sum() + b.q_len.sum()) == bases
     assert b.digest() == digest

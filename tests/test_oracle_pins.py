@@ -272,7 +272,7 @@ def test_long_gap_does_not_drop():
 
 
 def test_batch_matches_single():
-    b = seqgen.make_config(1, n_pairs=40)
+    b = seqgen.make_workload("uniform", n_pairs=40)
     out, cells = _batch_results(b)
     for p in range(b.n_pairs):
         r, c = oracle.align(b.target(p), b.query(p), b.scoring, b.w, b.zdrop)
