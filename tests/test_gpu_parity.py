@@ -202,6 +202,40 @@ def test_unsupported_band_raises():
     assert ei.value.code == ga.GA_EUNSUPPORTED
 
 
+def test_scores_at_the_range_guard():
+    """Two-million-base pairs with large scores, the range guard
+    (2 max_len + 2) * (max(a, b, ambig, q+e, q2+e2) + a + e + e2) + Z
+    < 2^29 filled to 97%: identical sequences, one with 1000 inserted bases
+    and an unrelated pair, with and without z-drop, bit-exact against the
+    oracle; one base more than the guard allows is refused before any
+    launch."""
+    import paper_2403_06478_amd as ga
+    sc = dict(a=30, b=60, q=40, e=20, q2=70, e2=5, ambig=40)
+    n, w = 2_000_000, 64
+    rng = np.random.default_rng(77)
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    t = acgt[rng.integers(0, 4, size=n)].tobytes()
+    ins = acgt[rng.integers(0, 4, size=1000)].tobytes()
+    other = acgt[rng.integers(0, 4, size=n)].tobytes()
+    b = seqgen.from_lists([t, t, t], [t, t[:n // 2] + ins + t[n // 2:], other], sc, w, 400)
+    P = max(sc["a"], sc["b"], sc["ambig"], sc["q"] + sc["e"], sc["q2"] + sc["e2"])
+    guard = (2 * (n + 1000) + 2) * (P + sc["a"] + sc["e"] + sc["e2"]) + 400
+    assert 0.95 * 2 ** 29 < guard < 2 ** 29
+    for Z in (400, -1):
+        _say(f"range guard: 3 pairs of {n} bases, w={w}, Z={Z}")
+        want, _ = oracle_align(b, Z=Z, scoring=sc)
+        got = gpu_align(b, Z=Z, scoring=sc)
+        assert_same(got, want, b, f"range guard Z={Z}")
+        assert got[0, 0] == sc["a"] * n and got[0, 1] == n - 1 and got[0, 2] == n - 1
+    k = P + sc["a"] + sc["e"] + sc["e2"]
+    over = -(-(2 ** 29) // (2 * k)) - 1  # the shortest max_len the guard refuses at Z=0
+    assert (2 * over + 2) * k >= 2 ** 29 > (2 * over) * k
+    big = acgt[rng.integers(0, 4, size=over)].tobytes()
+    with pytest.raises(ga.GaError) as ei:
+        gpu_align(seqgen.from_lists([big], [big[:100]], sc, w, 0), Z=0, scoring=sc)
+    assert ei.value.code == ga.GA_EINVAL
+
+
 @pytest.mark.parametrize("w", [1024, 1100, 1533, 1534, 2045, 2046, 3067, 3068, 4089])
 def test_multiwave_bands(w):
     """Bands wider than one wave holds (2w+1 > 2048 diagonals) run on 2-4
