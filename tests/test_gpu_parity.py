@@ -202,6 +202,28 @@ def test_unsupported_band_raises():
     assert ei.value.code == ga.GA_EUNSUPPORTED
 
 
+@pytest.mark.parametrize("sc", [
+    dict(a=27, b=228, q=60, e=20, q2=100, e2=5, ambig=228),  # every byte-table limit reached
+    dict(a=127, b=128, q=0, e=0, q2=0, e2=0, ambig=128),     # free gaps, extreme substitution scores
+    dict(a=1, b=0, q=0, e=1, q2=3, e2=0, ambig=0),           # free second piece: long gaps cost q2 only
+])
+def test_score_table_limits(sc):
+    """Scorings at the limits of the per-cell score bytes (S + q + 2e in
+    -128..127) and degenerate gap costs, bit-exact against the oracle with
+    and without z-drop; one past a limit is refused before any launch."""
+    import paper_2403_06478_amd as ga
+    b = seqgen.random_pairs(np.random.default_rng(sc["a"] + sc["b"]), 60, 0, 500, err=0.15, n_rate=0.05,
+                            related=0.7, scoring=sc, w=100, zdrop=200)
+    for Z in (200, -1):
+        want, _ = oracle_align(b, Z=Z, scoring=sc)
+        assert_same(gpu_align(b, Z=Z, scoring=sc), want, b, f"score limits {sc} Z={Z}")
+    fold = sc["q"] + 2 * sc["e"]
+    for past in (dict(sc, a=127 - fold + 1), dict(sc, b=fold + 129), dict(sc, ambig=fold + 129)):
+        with pytest.raises(ga.GaError) as ei:
+            gpu_align(b, scoring=past)
+        assert ei.value.code == ga.GA_EUNSUPPORTED
+
+
 def test_scores_at_the_range_guard():
     """Two-million-base pairs with large scores, the range guard
     (2 max_len + 2) * (max(a, b, ambig, q+e, q2+e2) + a + e + e2) + Z
