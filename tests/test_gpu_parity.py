@@ -429,6 +429,13 @@ def test_sliding_window_short_by_long(w):
         else:
             T.append(base)
             Q.append(short)
+    # short sides exactly at and one past each sliding window's limit
+    # (2s + 11 + K <= 64K: s <= 246 for K=8, s <= 498 for K=16), both ways
+    for s in (246, 247, 498, 499):
+        base = seq(b"ACGT", int(rng.integers(3000, 4000)))
+        short = base[100:100 + s]
+        T += [short, base]
+        Q += [base, short]
     for Z in (-1, 60, 400):
         b = seqgen.from_lists(T, Q, seqgen.SCORING, w, Z)
         cls = [ga.ga_pair_class(int(n), int(m), w) for n, m in zip(b.t_len, b.q_len)]
