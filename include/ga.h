@@ -262,7 +262,8 @@ int64_t ga_count_cells(int32_t n, int32_t m, int32_t w, int32_t r_end);
  * (unused pair entries are empty pairs). Whenever a slot is free, the
  * admitted requests waiting in its lane form its next batch, up to
  * max_batch_pairs pairs and max_batch_bases bases (long lane: long_*). A
- * server is driven from one host thread. */
+ * server is driven from one host thread; calls that touch the device make
+ * the server's device current for their duration and restore the caller's. */
 typedef struct {
     int32_t slots, long_slots;              /* execution slots per lane (>= 1) */
     int32_t max_batch_pairs, long_batch_pairs;

@@ -32,6 +32,19 @@ namespace {
 
 int64_t pad16(int64_t n) { return (n + 15) & ~int64_t(15); }
 
+// Makes the server's device current for a call and restores the caller's.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int device) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != device) (void)hipSetDevice(device);
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
 // Ring space handed out contiguously in arrival order (a request group that
 // does not fit before the end starts again at 0, the skipped end counting
 // as used) and released in any order; the oldest released regions are
@@ -367,7 +380,7 @@ int ga_server_create(ga_server_t **out, int device, const ga_scoring_t *sc, int3
 
 int ga_server_destroy(ga_server_t *srv) {
     if (!srv) return GA_EINVAL;
-    (void)hipSetDevice(srv->device);
+    DeviceScope ds(srv->device);
     for (Lane &L : srv->lanes) {
         for (Slot &s : L.slots) {
             for (Req *r : s.batch) delete r;
@@ -402,6 +415,7 @@ int ga_server_submit(ga_server_t *srv, int64_t tag, const uint8_t *target, int32
 
 int ga_server_poll(ga_server_t *srv, int64_t *tags, ga_result_t *results, double *t_done, int max_done) {
     if (!srv || max_done < 0 || (max_done > 0 && (!tags || !results))) return GA_EINVAL;
+    DeviceScope ds(srv->device);
     int nd = 0;
     int rc = GA_OK;
     for (Lane &L : srv->lanes) {
