@@ -219,8 +219,8 @@ __device__ __forceinline__ uint32_t window4(const uint32_t *W, int o) {
 template <int K>
 struct PairState {
     // Register vectors, so a slot at a wave-uniform position (the band wall,
-    // a cell leaving the rectangle) can be indexed (s_set_gpr_idx) without
-    // leaving registers.
+    // a cell leaving the rectangle) can be indexed without leaving registers
+    // (s_set_gpr_idx from 16 slots up, a select per slot below that).
     typedef int VecK __attribute__((ext_vector_type(K)));
     VecK A, E, X, F, Y;
     uint32_t S4[K];  // s' of the slot's next 4 cells, one signed byte each
