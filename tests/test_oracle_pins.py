@@ -71,6 +71,20 @@ def test_closed_forms(case):
       (ceil((r-500)/2), ...)) first holds at r = 851: M = -901 at (176, 675).
       This case also fixes the slope of the z-drop rule to e2: with e = 2 the
       threshold at r = 851 would be 1398.
+    * Strictness of i' < i and j' < j (Eq. 5), T = G^4 C^6, Q = G^4 with the
+      benchmark scoring (gamma(l) = 4 + 2l for l <= 20), Z = 5, a band wider
+      than both: even r = 2k <= 6 has the unique maximum 2(k+1) on (k,k), so
+      G = 8 at (3,3) after r = 6. Odd r = 2k+1 <= 5 ties at 2(k+1) - gamma(1)
+      on (k,k+1) and (k+1,k); the smallest i is (k,k+1), with
+      G - M = 6 = Z + e2*1, so nothing drops there under either reading.
+      The query ends at j = 3: for r = 6 + l the cells are (r-j, j), j <= 3,
+      and the best is the vertical gap (3+l, 3) at 8 - gamma(l) (matching
+      fewer G or placing C against G only costs more), which lies in G's
+      column: mi > gi but mj = gj, so the strict rule never tests it and the
+      sweep ends on the last anti-diagonal r = 12 at (9,3), 8 - gamma(6) = -8,
+      after all 40 cells. A non-strict rule would test it: at r = 8,
+      G - M = gamma(2) = 8 > Z + e2*2 = 7, a drop at (5,3). Swapping T and Q
+      puts the same maxima in G's row (mi = gi) and pins i' < i.
     """
     res, cells = oracle.align(case["T"], case["Q"], case["sc"], case["w"], case["Z"])
     assert res == case["res"]
