@@ -9,6 +9,8 @@ import oracle
 import paper_2403_06478_amd as ga
 
 _CTX = None
+_TUNED = None
+_WORKLOADS = {}
 
 
 def context():
@@ -18,9 +20,26 @@ def context():
     return _CTX
 
 
-def gpu_align(batch, w=None, Z=None, scoring=None):
+def tuned_context():
+    """A context with the autotuned class order, as the benchmark runs."""
+    global _TUNED
+    if _TUNED is None:
+        _TUNED = ga.Context(0)
+        _TUNED.autotune()
+    return _TUNED
+
+
+def workload(name):
+    """A full synthetic workload at seed 0, drawn once per test process."""
+    import seqgen
+    if name not in _WORKLOADS:
+        _WORKLOADS[name] = seqgen.make_workload(name)
+    return _WORKLOADS[name]
+
+
+def gpu_align(batch, w=None, Z=None, scoring=None, ctx=None):
     import torch
-    ctx = context()
+    ctx = ctx or context()
     packed = ga.pack_batch(ctx, batch)
     out = ga.ga_align_batch(ctx, packed, scoring or batch.scoring,
                             batch.w if w is None else w, batch.zdrop if Z is None else Z)

@@ -11,9 +11,11 @@ import pytest
 
 import seqgen
 from brute import band_cells
-from gpu_util import assert_same, gpu_align, oracle_align
+from gpu_util import assert_same, gpu_align, oracle_align, tuned_context, workload
 
 pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def _say(msg):
@@ -108,10 +110,44 @@ def test_mix_sample():
     assert got[:, 6].sum() >= 1
 
 
+@pytest.mark.parametrize("name", ["uniform", "ont", "mix", "longread", "serving"])
+def test_full_workload_every_pair(name):
+    """Every pair of each full synthetic workload, run in one call with the
+    autotuned class order (as the benchmark times it), against the oracle's
+    results stored as one SHA-256 per 1000-pair chunk
+    (tests/golden/oracle_digests.txt, written on the CPU by
+    make_oracle_digests.py beside it). A chunk that differs is re-aligned by
+    the oracle here and its differing pairs are named."""
+    import paper_2403_06478_amd as ga
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from make_oracle_digests import chunk_digests, read_digests
+    ref = read_digests()[name]
+    b = workload(name)
+    assert b.n_pairs == ref["pairs"] and b.digest() == ref["digest"], "inputs differ from the digests' inputs"
+    _say(f"every pair of {name}: {b.n_pairs} pairs, w={b.w} Z={b.zdrop}")
+    got = gpu_align(b, ctx=tuned_context())
+    C = ref["chunk"]
+    mine = chunk_digests(got, C)
+    bad = [k for k, (x, y) in enumerate(zip(mine, ref["chunks"])) if x != y]
+    if bad:
+        k = bad[0]
+        idx = np.arange(k * C, min(b.n_pairs, (k + 1) * C))
+        sub = b.subset(idx)
+        want, _ = oracle_align(sub)
+        assert_same(got[idx], want, sub, f"{name}: {len(bad)} of {len(mine)} chunks differ; chunk {k}")
+        raise AssertionError(f"{name}: chunk {k} digest differs but its pairs match the oracle run here")
+    assert len(mine) == len(ref["chunks"])
+    assert int(got[:, 6].sum()) == ref["zdropped"]
+    cells = ga.count_cells(b.t_len, b.q_len, b.w, got)
+    assert int(cells.sum()) == ref["cells"]
+    _say(f"every pair of {name}: {len(mine)} chunks equal, {int(cells.sum())} cells, "
+          f"{ref['zdropped']} z-dropped")
+
+
 def test_ont_like_100k_full_size_sampled():
     """The bench workload at full size (100k pairs, one launch): sampled
     pairs against the oracle, every pair against cheap properties."""
-    b = seqgen.make_workload("ont")
+    b = workload("ont")
     _say(f"ONT-like full: {b.n_pairs} pairs")
     got = gpu_align(b)
     rng = np.random.default_rng(2)
@@ -136,7 +172,7 @@ def test_mix_1m_full_size_sampled():
     that dropped and short-by-long pairs against the oracle; every pair
     against cheap properties."""
     import paper_2403_06478_amd as ga
-    b = seqgen.make_workload("mix")
+    b = workload("mix")
     _say(f"mix full: {b.n_pairs} pairs")
     got = gpu_align(b)
     rng = np.random.default_rng(3)
@@ -304,7 +340,7 @@ def test_long_reads_sample():
 def test_long_reads_20k_full_size_sampled():
     """The whole 20k-pair long-read workload in one launch: sampled pairs
     against the oracle, every pair against cheap properties."""
-    b = seqgen.make_workload("longread")
+    b = workload("longread")
     _say(f"long-read full: {b.n_pairs} pairs")
     got = gpu_align(b)
     rng = np.random.default_rng(4)
@@ -667,6 +703,42 @@ def test_graph_replays_match_eager():
         slot.ctx.close()
 
 
+def test_autotune_order_and_results():
+    """The autotuner measures every class; afterwards each pair takes the
+    cheapest (by the measured costs) allowed class that runs it, and the
+    results under the tuned order stay those of the oracle on a batch that
+    spans every fixed, sliding and multi-wave class of the mixed workload."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    ctx = ga.Context(0)
+    cost = ctx.autotune()
+    _say("autotune: " + ", ".join(f"{ga.class_name(c)}={cost[c]:.3f}" for c in range(len(cost))))
+    assert len(cost) == len(ga.CLASSES) and all(np.isfinite(cost)) and min(cost) > 0
+    rng = np.random.default_rng(61)
+    every = range(len(ga.CLASSES))
+    for _ in range(2000):
+        n, m = (int(x) for x in rng.integers(1, 9000, 2))
+        w = int(rng.choice([-1, 50, 300, 751, 1000, 1500, 2500, 3500]))
+        holders = [c for c in every if ga.ga_pair_class_in(n, m, w, [c]) == c]
+        got = ctx.pair_class(n, m, w)
+        if not holders:
+            assert got == -1
+            continue
+        assert got in holders and cost[got] == min(cost[c] for c in holders), (n, m, w, got, holders)
+    full = seqgen.make_workload("mix", n_pairs=3000, seed=5)
+    b = full.subset(np.nonzero(full.t_len <= 6000)[0][:1200])
+    classes = sorted({ctx.pair_class(int(n), int(m), b.w) for n, m in zip(b.t_len, b.q_len)})
+    _say(f"autotuned mix sample: {b.n_pairs} pairs in classes {classes}")
+    packed = ga.pack_batch(ctx, b)
+    out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+    torch.cuda.synchronize()
+    ctx.check()
+    want, _ = oracle_align(b)
+    assert_same(out.cpu().numpy(), want, b, "autotuned mix sample")
+    ctx.close()
+
+
 def test_lanes_same_results():
     """Spreading the class launches over one, two or three streams gives the
     same results (checked against the oracle on a mixed sample)."""
@@ -744,4 +816,16 @@ def test_native_server():
     assert np.array_equal(np.array([got[k] for k in range(20)]), want[:20])
     huge = b"A" * 200000
     assert lib.ga_server_submit(srv._h, 99, huge, len(huge), b"A", 1, -1.0) == ga.GA_EUNSUPPORTED
+    # a collection buffer smaller than a slot's capacity (8 pairs) is refused
+    assert lib.ga_server_poll(srv._h, tags.ctypes.data, out.ctypes.data, None, 7) == ga.GA_EINVAL
+    assert lib.ga_server_poll(srv._h, tags.ctypes.data, out.ctypes.data, None, 0) == ga.GA_OK
+    srv.close()
+    # the replay deadline, forced from the host: a timeout far below one
+    # batch's run returns GA_EHIP once requests are in flight; the batch
+    # itself completes normally before the server is released
+    long_k = int(np.argmax(b.t_len + b.q_len))
+    srv = serve.NativeServer(b.scoring, b.w, b.zdrop, 0, graphs=False, replay_timeout_s=1e-6, **kw)
+    with pytest.raises(ga.GaError) as ei:
+        srv.replay(b, np.zeros(4), pairs=np.full(4, long_k))
+    assert ei.value.code == ga.GA_EHIP
     srv.close()
