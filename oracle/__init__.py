@@ -23,6 +23,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ga_oracle.c")
 _LIB = os.path.join(_HERE, "_oracle.so")
+# The same source built for the host it runs on (-O3 -march=native): the
+# CPU baseline's timing build and the build that computes stored digests.
+# Integer arithmetic only, so both builds give identical results; the
+# portable one is what the tests load.
+_LIB_NATIVE = os.path.join(_HERE, "_oracle_native.so")
 
 RESULT_FIELDS = ("max_score", "max_i", "max_j", "end_score", "end_i", "end_j", "zdropped")
 
@@ -35,26 +40,31 @@ class Result(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in RESULT_FIELDS]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (portable flags: the library may run on
-    another host than the one that built it)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC]
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc: portable flags by default (the library
+    may run on another host than the one that built it), or with ``native``
+    -O3 -march=native for the host compiling it (build it on the host that
+    runs it)."""
+    path = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + f".tmp{os.getpid()}"
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        cmd = ["gcc"] + opt + ["-std=c11", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, path)
+    return path
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+def _load(native: bool = False):
+    lib = _libs.get(native)
+    if lib is None:
+        path = _LIB_NATIVE if native else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(force=True, native=native)
+        lib = ctypes.CDLL(path)
         lib.oracle_align.restype = ctypes.c_int
         lib.oracle_align.argtypes = [
             ctypes.c_char_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
@@ -65,8 +75,8 @@ def _load():
         lib.oracle_align_batch.argtypes = [
             ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Scoring),
             ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int32]
-        _lib = lib
-    return _lib
+        _libs[native] = lib
+    return lib
 
 
 def scoring(sc: dict) -> Scoring:
@@ -86,11 +96,12 @@ def align(T: bytes, Q: bytes, sc: dict, w: int, Z: int) -> Tuple[Tuple[int, ...]
 
 
 def align_batch(batch, nthreads: Optional[int] = None, w: Optional[int] = None,
-                Z: Optional[int] = None, sc: Optional[dict] = None):
-    """Align every pair of a ``seqgen.PairBatch``.
+                Z: Optional[int] = None, sc: Optional[dict] = None, native: bool = False):
+    """Align every pair of a ``seqgen.PairBatch`` (``native``: the
+    -O3 -march=native build of the same source).
 
     Returns (results int32[n_pairs, 7], cells int64[n_pairs])."""
-    lib = _load()
+    lib = _load(native)
     n = batch.n_pairs
     out = np.zeros((n, 7), dtype=np.int32)
     cells = np.zeros(n, dtype=np.int64)
