@@ -265,19 +265,30 @@ int64_t ga_count_cells(int32_t n, int32_t m, int32_t w, int32_t r_end);
  * server is driven from one host thread; calls that touch the device make
  * the server's device current for their duration and restore the caller's. */
 typedef struct {
-    int32_t slots, long_slots;              /* execution slots per lane (>= 1) */
-    int32_t max_batch_pairs, long_batch_pairs;
+    int32_t slots, long_slots;              /* execution slots per lane (1 .. GA_SERVER_MAX_SLOTS) */
+    int32_t max_batch_pairs, long_batch_pairs; /* 1 .. GA_SERVER_MAX_BATCH_PAIRS */
     int64_t max_batch_bases, long_batch_bases;
     int32_t long_bases;                     /* requests with more bases go to the long lane */
-    int32_t ring_factor;                    /* ring bytes = ring_factor x the lane's batch bases */
+    int32_t ring_factor;                    /* ring bytes = ring_factor x the lane's batch bases
+                                               (at most GA_SERVER_MAX_RING_BYTES) */
     int32_t graphs;                         /* 1: replay a captured graph per batch */
+    double replay_timeout_s;                /* ga_server_replay gives up after this long with
+                                               requests in flight and no batch finished;
+                                               0: GA_SERVER_REPLAY_TIMEOUT_S */
 } ga_server_config_t;
+
+#define GA_SERVER_MAX_SLOTS 16
+#define GA_SERVER_MAX_BATCH_PAIRS (1 << 20)
+#define GA_SERVER_MAX_RING_BYTES ((int64_t)1 << 33)
+#define GA_SERVER_REPLAY_TIMEOUT_S 60.0
 
 typedef struct ga_server ga_server_t;
 
 /* Create a server on `device` for one scoring, band and threshold (see
  * ga_align_batch). Allocates every buffer and captures the graphs now.
- * GA_EINVAL for a bad configuration, GA_ENOMEM, GA_EHIP. */
+ * GA_EINVAL for a bad configuration (checked before any device work: counts
+ * below 1 or above the GA_SERVER_MAX_* limits, a negative timeout),
+ * GA_ENOMEM, GA_EHIP. */
 int ga_server_create(ga_server_t **srv, int device, const ga_scoring_t *sc, int32_t w, int32_t Z,
                      const ga_server_config_t *cfg);
 
@@ -294,8 +305,14 @@ int ga_server_submit(ga_server_t *srv, int64_t tag, const uint8_t *target, int32
 /* Make progress without waiting: collect finished batches (writing up to
  * max_done (tag, result, completion time) triples; a batch is collected
  * only when all of it fits), admit waiting requests, start batches on free
- * slots. Returns the number of results written, or a negative GA_* code
- * (GA_EDEVICE if a device-side check failed for a collected batch). */
+ * slots. max_done is 0 (collect nothing) or at least the larger of
+ * max_batch_pairs and long_batch_pairs (else GA_EINVAL). Returns the number
+ * of results written. Errors never cost results: an error found while
+ * results are handed back (GA_EDEVICE for a collected batch with pairs
+ * outside the declared bounds, which got the sentinel result; GA_EHIP for a
+ * batch whose completion cannot be queried, which stays in its slot; a
+ * failed launch, whose requests wait again) is latched, and the next poll
+ * that writes no results returns it (and clears it). */
 int ga_server_poll(ga_server_t *srv, int64_t *tags, ga_result_t *results, double *t_done, int max_done);
 
 /* Requests submitted and not yet collected; batches launched so far. */
@@ -306,7 +323,9 @@ int64_t ga_server_batches(const ga_server_t *srv);
  * target bytes t_ascii[t_off[k] .. +t_len[k]), query likewise -- arrives
  * arrival_s[k] seconds (non-decreasing) after the start; the call submits
  * each at its time, polls until all are done and writes results[k] and
- * latency_s[k] (arrival to collection), and the wall time. */
+ * latency_s[k] (arrival to collection), and the wall time. Returns GA_EHIP
+ * if requests stay in flight for the configured timeout with no batch
+ * finishing, or the first error a poll returns. */
 int ga_server_replay(ga_server_t *srv, const uint8_t *t_ascii, const int64_t *t_off, const int32_t *t_len,
                      const uint8_t *q_ascii, const int64_t *q_off, const int32_t *q_len, const double *arrival_s,
                      int64_t n, ga_result_t *results, double *latency_s, double *wall_s);

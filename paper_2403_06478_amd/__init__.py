@@ -78,6 +78,7 @@ class ServerConfig(ctypes.Structure):
         ("max_batch_pairs", ctypes.c_int32), ("long_batch_pairs", ctypes.c_int32),
         ("max_batch_bases", ctypes.c_int64), ("long_batch_bases", ctypes.c_int64),
         ("long_bases", ctypes.c_int32), ("ring_factor", ctypes.c_int32), ("graphs", ctypes.c_int32),
+        ("replay_timeout_s", ctypes.c_double),
     ]
 
 

@@ -150,6 +150,8 @@ struct ga_server {
     Lane lanes[2];
     int64_t batches = 0;
     int64_t in_flight = 0;  // submitted, not yet finished
+    int64_t max_capacity = 0;  // pairs of the largest slot
+    int err = GA_OK;           // first error found while results were handed back
 };
 
 namespace {
@@ -314,7 +316,12 @@ int launch(ga_server *srv, Slot &s) {
         rc = device_steps(srv, s, s.stream);
     }
     if (rc == GA_OK && hipEventRecord(s.done, s.stream) != hipSuccess) rc = GA_EHIP;
-    if (rc != GA_OK) return rc;
+    if (rc != GA_OK) {
+        // nothing of this batch runs: its requests wait again, in order
+        for (int64_t k = n - 1; k >= 0; --k) L.admitted.push_front(s.batch[k]);
+        s.batch.clear();
+        return rc;
+    }
     s.busy = true;
     ++srv->batches;
     return GA_OK;
@@ -333,7 +340,13 @@ int ga_server_create(ga_server_t **out, int device, const ga_scoring_t *sc, int3
     if (!out || !sc || !cfg) return GA_EINVAL;
     *out = nullptr;
     if (cfg->slots < 1 || cfg->long_slots < 1 || cfg->max_batch_pairs < 1 || cfg->long_batch_pairs < 1 ||
-        cfg->max_batch_bases < 1 || cfg->long_batch_bases < 1 || cfg->ring_factor < 1 || cfg->long_bases < 0)
+        cfg->max_batch_bases < 1 || cfg->long_batch_bases < 1 || cfg->ring_factor < 1 || cfg->long_bases < 0 ||
+        !(cfg->replay_timeout_s >= 0))
+        return GA_EINVAL;
+    if (cfg->slots > GA_SERVER_MAX_SLOTS || cfg->long_slots > GA_SERVER_MAX_SLOTS ||
+        cfg->max_batch_pairs > GA_SERVER_MAX_BATCH_PAIRS || cfg->long_batch_pairs > GA_SERVER_MAX_BATCH_PAIRS ||
+        cfg->max_batch_bases > GA_SERVER_MAX_RING_BYTES / cfg->ring_factor ||
+        cfg->long_batch_bases > GA_SERVER_MAX_RING_BYTES / cfg->ring_factor)
         return GA_EINVAL;
     ga_server *srv = new (std::nothrow) ga_server;
     if (!srv) return GA_ENOMEM;
@@ -342,6 +355,7 @@ int ga_server_create(ga_server_t **out, int device, const ga_scoring_t *sc, int3
     srv->w = w;
     srv->Z = Z;
     srv->cfg = *cfg;
+    srv->max_capacity = cfg->max_batch_pairs > cfg->long_batch_pairs ? cfg->max_batch_pairs : cfg->long_batch_pairs;
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (hipSetDevice(device) != hipSuccess) {
@@ -415,17 +429,27 @@ int ga_server_submit(ga_server_t *srv, int64_t tag, const uint8_t *target, int32
 
 int ga_server_poll(ga_server_t *srv, int64_t *tags, ga_result_t *results, double *t_done, int max_done) {
     if (!srv || max_done < 0 || (max_done > 0 && (!tags || !results))) return GA_EINVAL;
+    // a batch is handed back whole: a buffer smaller than a slot's capacity
+    // could leave that slot's results uncollected for ever
+    if (max_done > 0 && max_done < srv->max_capacity) return GA_EINVAL;
     DeviceScope ds(srv->device);
     int nd = 0;
-    int rc = GA_OK;
+    auto latch = [srv](int code) {
+        if (srv->err == GA_OK) srv->err = code;
+    };
     for (Lane &L : srv->lanes) {
         for (Slot &s : L.slots) {
             if (!s.busy || (int64_t)(max_done - nd) < (int64_t)s.batch.size()) continue;
             const hipError_t q = hipEventQuery(s.done);
             if (q == hipErrorNotReady) continue;
-            if (q != hipSuccess) return GA_EHIP;
+            if (q != hipSuccess) {
+                latch(GA_EHIP);  // its results are not known to be complete: left in the slot
+                continue;
+            }
+            // pairs outside the declared bounds got the sentinel result;
+            // the rest of the batch is valid and is handed back
             const int crc = ga_context_check(s.ctx, s.stream);
-            if (crc != GA_OK && rc == GA_OK) rc = crc;
+            if (crc != GA_OK) latch(crc);
             const double t = now_s();
             for (size_t k = 0; k < s.batch.size(); ++k) {
                 Req *r = s.batch[k];
@@ -448,11 +472,17 @@ int ga_server_poll(ga_server_t *srv, int64_t *tags, ga_result_t *results, double
             if (L.admitted.empty()) break;
             if (!s.busy) {
                 const int lrc = launch(srv, s);
-                if (lrc != GA_OK) return lrc;
+                if (lrc != GA_OK) {
+                    latch(lrc);
+                    break;
+                }
             }
         }
     }
-    return rc != GA_OK ? rc : nd;
+    if (nd > 0) return nd;
+    const int e = srv->err;
+    srv->err = GA_OK;
+    return e;
 }
 
 int64_t ga_server_pending(const ga_server_t *srv) { return srv ? srv->in_flight : -1; }
@@ -467,20 +497,28 @@ int ga_server_replay(ga_server_t *srv, const uint8_t *t_ascii, const int64_t *t_
         return GA_EINVAL;
     const double t0 = now_s();
     int64_t next = 0, finished = 0;
-    const int cap = 8192;
+    // room for every slot's batch at once (ga_server_create bounds both)
+    const int64_t cap64 = srv->cfg.slots * (int64_t)srv->cfg.max_batch_pairs +
+                          srv->cfg.long_slots * (int64_t)srv->cfg.long_batch_pairs;
+    const int cap = (int)cap64;
     std::vector<int64_t> tags(cap);
     std::vector<ga_result_t> res(cap);
     std::vector<double> td(cap);
+    const double timeout = srv->cfg.replay_timeout_s > 0 ? srv->cfg.replay_timeout_s : GA_SERVER_REPLAY_TIMEOUT_S;
+    double progress = now_s();  // the last submission or collection
     while (finished < n) {
         const double now = now_s() - t0;
+        if (srv->in_flight > 0 && now_s() - progress > timeout) return GA_EHIP;  // no batch finished in time
         while (next < n && arrival_s[next] <= now) {
             const int rc = ga_server_submit(srv, next, t_ascii + t_off[next], t_len[next], q_ascii + q_off[next],
                                             q_len[next], t0 + arrival_s[next]);
             if (rc != GA_OK) return rc;
             ++next;
+            progress = now_s();
         }
         const int nd = ga_server_poll(srv, tags.data(), res.data(), td.data(), cap);
         if (nd < 0) return nd;
+        if (nd > 0) progress = now_s();
         for (int k = 0; k < nd; ++k) {
             const int64_t i = tags[k];
             results[i] = res[k];

@@ -388,12 +388,12 @@ class NativeServer:
     def __init__(self, scoring: dict, w: int, Z: int, device: int = 0, slots: int = 2, long_slots: int = 1,
                  max_batch_pairs: int = 256, max_batch_bases: int = 1_000_000, long_bases: int = 8000,
                  long_batch_pairs: int = 4096, long_batch_bases: int = 16_000_000, graphs: bool = True,
-                 ring_factor: int = 4):
+                 ring_factor: int = 4, replay_timeout_s: float = 0.0):
         _torch()  # the HIP runtime torch uses, and a device
         self.lib = load_library()
         cfg = ServerConfig(int(slots), int(long_slots), int(max_batch_pairs), int(long_batch_pairs),
                            int(max_batch_bases), int(long_batch_bases), int(long_bases), int(ring_factor),
-                           1 if graphs else 0)
+                           1 if graphs else 0, float(replay_timeout_s))
         sc = scoring_struct(scoring)
         h = ctypes.c_void_p()
         _check(self.lib.ga_server_create(ctypes.byref(h), int(device), ctypes.byref(sc), int(w), int(Z),
@@ -449,11 +449,13 @@ def serve_trace_native(batch, arrivals: np.ndarray, device: int = 0, pairs=None,
     return res, lat, wall, nb
 
 
-def serve_trace(batch, arrivals: np.ndarray, device: int = 0, pairs=None, **server_args):
+def serve_trace(batch, arrivals: np.ndarray, device: int = 0, pairs=None, timeout_s: float = 60.0,
+                **server_args):
     """Replay a request trace: request k (pair ``pairs[k]`` of ``batch``,
     pair k without ``pairs``) arrives at ``arrivals[k]`` seconds after the
     start. Returns (results [n, 7], latencies in seconds, wall seconds,
-    batches launched)."""
+    batches launched); raises TimeoutError when requests stay in flight for
+    ``timeout_s`` seconds with no batch finishing."""
     n = int(np.asarray(arrivals).shape[0])
     sel = np.arange(batch.n_pairs) if pairs is None else np.asarray(pairs, dtype=np.int64)
     if sel.shape[0] != n:
@@ -465,16 +467,22 @@ def serve_trace(batch, arrivals: np.ndarray, device: int = 0, pairs=None, **serv
     nxt = 0
     finished = 0
     t0 = time.perf_counter()
+    progress = t0  # the last submission or collection
     while finished < n:
         now = time.perf_counter() - t0
+        if not srv.idle and time.perf_counter() - progress > timeout_s:
+            srv.close()
+            raise TimeoutError(f"no batch finished in {timeout_s} s with requests in flight")
         while nxt < n and arrivals[nxt] <= now:
             t_arr[nxt] = t0 + arrivals[nxt]
             srv.submit(nxt, batch.target(int(sel[nxt])), batch.query(int(sel[nxt])), t_arr[nxt])
             nxt += 1
+            progress = time.perf_counter()
         for rid, row, t in srv.step():
             results[rid] = row
             t_done[rid] = t
             finished += 1
+            progress = time.perf_counter()
         if nxt < n and srv.idle:
             # nothing in flight: sleep until the next arrival (bounded)
             time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))

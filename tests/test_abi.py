@@ -199,3 +199,39 @@ def test_ring_space():
         pass
     else:
         raise AssertionError("oversized request accepted")
+
+
+def test_server_config_validation_without_gpu():
+    """ga_server_create refuses a bad configuration before any device work:
+    counts below 1 or above the GA_SERVER_MAX_* limits of the header, a ring
+    larger than its limit, a negative replay timeout; the other entry points
+    refuse a null server."""
+    lib = ga.load_library()
+    sc = ga.scoring_struct(dict(a=2, b=4, q=4, e=2, q2=24, e2=1, ambig=1))
+    text = open(HEADER).read()
+    max_slots, max_pairs = 16, 1 << 20
+    assert "#define GA_SERVER_MAX_SLOTS 16" in text
+    assert "#define GA_SERVER_MAX_BATCH_PAIRS (1 << 20)" in text
+    assert "#define GA_SERVER_MAX_RING_BYTES ((int64_t)1 << 33)" in text
+
+    def cfg(**kw):
+        base = dict(slots=2, long_slots=1, max_batch_pairs=256, long_batch_pairs=4096, max_batch_bases=10 ** 6,
+                    long_batch_bases=16 * 10 ** 6, long_bases=8000, ring_factor=4, graphs=1, replay_timeout_s=0.0)
+        base.update(kw)
+        return ga.ServerConfig(*(base[k] for k, _ in ga.ServerConfig._fields_))
+
+    bad = [dict(slots=0), dict(long_slots=0), dict(slots=max_slots + 1), dict(max_batch_pairs=0),
+           dict(long_batch_pairs=max_pairs + 1), dict(max_batch_pairs=max_pairs + 1), dict(ring_factor=0),
+           dict(max_batch_bases=0), dict(long_batch_bases=(1 << 33) // 4 + 1), dict(long_bases=-1),
+           dict(replay_timeout_s=-1.0), dict(replay_timeout_s=float("nan"))]
+    for kw in bad:
+        h = ctypes.c_void_p()
+        c = cfg(**kw)
+        assert lib.ga_server_create(ctypes.byref(h), 0, ctypes.byref(sc), 500, 400, ctypes.byref(c)) == ga.GA_EINVAL, kw
+        assert not h.value
+    h = ctypes.c_void_p()
+    assert lib.ga_server_create(ctypes.byref(h), 0, None, 500, 400, ctypes.byref(cfg())) == ga.GA_EINVAL
+    assert lib.ga_server_poll(None, None, None, None, 0) == ga.GA_EINVAL
+    assert lib.ga_server_submit(None, 0, b"A", 1, b"A", 1, -1.0) == ga.GA_EINVAL
+    assert lib.ga_server_destroy(None) == ga.GA_EINVAL
+    assert lib.ga_server_pending(None) == -1
