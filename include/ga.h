@@ -30,8 +30,8 @@
  * bound, offsets outside the packed streams) are latched in the context and
  * reported by ga_context_check().
  *
- * A context serves one call at a time: its workspace (unpacked bases,
- * planning counters, the error latch) is reused by every ga_pack and
+ * A context serves one call at a time: its workspace (planning counters
+ * and work lists, the error latch) is reused by every ga_pack and
  * ga_align_batch on it, so calls on one context must be ordered on the
  * device (issued on one stream, or with the caller's synchronisation
  * between streams) and made from one host thread at a time. Work that
@@ -91,7 +91,7 @@ typedef struct {
 typedef struct ga_context ga_context_t;
 
 /* Create a context on HIP device `device`; it owns the device workspace
- * (unpacked bases, work lists, counters). Returns GA_EINVAL for a bad device. */
+ * (work lists, counters: about 1 MiB plus 8 bytes per pair). Returns GA_EINVAL for a bad device. */
 int ga_context_create(ga_context_t **ctx, int device);
 
 /* Release the context and its workspace (synchronises the device). */
@@ -164,18 +164,19 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_
 int ga_context_set_schedule(ga_context_t *ctx, int schedule);
 
 /* Streams the persistent launches of one ga_align_batch call spread over
- * (1..3; default 3): the caller's stream plus up to two streams the context
- * owns, forked from and joined back into the caller's stream, so the call
- * stays ordered on `stream` while the launches of different kernel classes
- * overlap on the device (the tail of one class -- its last, longest pairs
- * -- runs beside the next). 1 keeps every launch on `stream` (e.g. where
- * many contexts share the GPU's few hardware queues). GA_EINVAL outside
- * 1..3. */
+ * (1..4; default 4): the caller's stream plus up to three streams the
+ * context owns, forked from and joined back into the caller's stream, so the
+ * call stays ordered on `stream` while the launches of different kernel
+ * classes overlap on the device. The class holding the band's full width
+ * (where a batch's longest pairs land) launches first, on the caller's
+ * stream, so its longest pairs start at once. 1 keeps every launch on
+ * `stream` (e.g. where many contexts share the GPU's few hardware queues).
+ * GA_EINVAL outside 1..4. */
 int ga_context_set_lanes(ga_context_t *ctx, int lanes);
 
 /* Restrict the kernel classes (bit c = class c, see ga_context_timing) that
  * later ga_align_batch calls on this context may use; the default is all
- * eleven. Each pair takes the cheapest allowed class that runs it in the
+ * twelve. Each pair takes the cheapest allowed class that runs it in the
  * shape the cheapest-first rule gives that class (a sliding class only for a
  * band wider than its window, a class of W waves only for a band that
  * reaches its last wave: more than 64*K*(W-1) diagonals). A pair that no
@@ -183,7 +184,7 @@ int ga_context_set_lanes(ga_context_t *ctx, int lanes);
  * GA_EDEVICE (see ga_context_check). For sensitivity studies of the kernel
  * shapes (the slice width of Section 5.5 and the subwarp size of Section 5.7 have
  * their counterparts in the slots per lane and the waves per pair). Returns
- * GA_EINVAL for an empty mask or bits above class 10. */
+ * GA_EINVAL for an empty mask or bits above class 11. */
 int ga_context_set_classes(ga_context_t *ctx, uint32_t mask);
 
 /* Autotuner (the context's autotune table): runs a synthetic probe batch
@@ -191,7 +192,7 @@ int ga_context_set_classes(ga_context_t *ctx, uint32_t mask);
  * about one substitution in 16, in the shape the cheapest-first rule gives
  * each class (the band filling 7/8 of its slots; short-by-long pairs for the
  * sliding classes), enough pairs for two rounds of resident workgroups --
- * and times each class's launch. ns_per_step[c] (c < n, n <= 11) receives
+ * and times each class's launch. ns_per_step[c] (c < n, n <= 12) receives
  * the measured cost of class c in nanoseconds per pair and anti-diagonal at
  * full occupancy. Later ga_align_batch calls on this context then try the
  * classes cheapest first: each pair takes the cheapest allowed class that
@@ -210,24 +211,26 @@ int ga_context_pair_class(const ga_context_t *ctx, int32_t n, int32_t m, int32_t
 int ga_context_set_timing(ga_context_t *ctx, int enable);
 
 /* Milliseconds spent by the stages of the last timed ga_align_batch on this
- * context (waits for those events): ms[0] = unpack + planning kernels,
+ * context (waits for those events): ms[0] = planning kernels,
  * ms[1+c] = the alignment launches of class c (summed over buckets under
- * GA_SCHED_BUCKETED), for c < n-1 and c < 11. Class
- * c runs K slots per lane and W waves per pair: (K, W) = (4,1) (8,1) (16,1)
- * (24,1) (32,1) hold bands of up to 64*K diagonals; (8,1) (16,1) with a
- * sliding window run pairs whose shorter sequence s has 2s + 11 + K <= 64K
- * whatever the band; (24,2) (32,2) (32,3) (32,4) hold bands of up to
+ * GA_SCHED_BUCKETED), for c < n-1 and c < 12. Class
+ * c runs K slots per lane and W waves per pair: classes 0-4, (K, W) = (4,1)
+ * (8,1) (16,1) (24,1) (32,1), hold bands of up to 64*K diagonals; classes
+ * 5, 6 and 11, (8,1) (16,1) (4,1) with a sliding window, run pairs whose
+ * shorter sequence s has 2s + 11 + K <= 64K whatever the band; classes
+ * 7-10, (24,2) (32,2) (32,3) (32,4), hold bands of up to
  * 64*K + (W-1)*(64*K - 4) diagonals (3068, 4092, 6136, 8180: neighbouring
  * waves share 4 diagonals).
  * GA_EINVAL if timing was off for that call. */
 int ga_context_timing(ga_context_t *ctx, float *ms, int n);
 
-/* Class (0..10, see ga_context_timing) that ga_align_batch uses for a pair
+/* Class (0..11, see ga_context_timing) that ga_align_batch uses for a pair
  * of lengths n, m at band w: the cheapest whose kernel holds the band's
  * min(w, n) + min(w, m) + 1 diagonals (all n + m + 1 when w < 0), or, for a
  * sliding class, the pair's 2 min(n, m) + 11 + K; -1 for an empty pair or
  * a band wider than the kernels hold. Cheapest means fewest slots per lane
- * (4, 8, sliding 8, 16, sliding 16, 24, 32), then the multi-wave classes.
+ * (4, sliding 4, 8, sliding 8, 16, sliding 16, 24, 32), then the multi-wave
+ * classes.
  * Host function, for attributing work to the per-class kernels. */
 int ga_pair_class(int32_t n, int32_t m, int32_t w);
 

@@ -45,7 +45,8 @@ SCHEDULES = {"persistent": GA_SCHED_PERSISTENT, "bucketed": GA_SCHED_BUCKETED, "
 # window). A fixed class holds bands of up to 64 * K * waves diagonals; a
 # sliding one-wave class runs a short-by-long pair whose band is wider.
 CLASSES = ((4, 1, False), (8, 1, False), (16, 1, False), (24, 1, False), (32, 1, False),
-           (8, 1, True), (16, 1, True), (24, 2, False), (32, 2, False), (32, 3, False), (32, 4, False))
+           (8, 1, True), (16, 1, True), (24, 2, False), (32, 2, False), (32, 3, False), (32, 4, False),
+           (4, 1, True))
 CLASS_SLOTS = tuple(k for k, _, _ in CLASSES)
 def class_capacity(c: int) -> int:
     """Diagonals class c holds: 64 K on one wave; neighbouring waves of a
@@ -54,7 +55,7 @@ def class_capacity(c: int) -> int:
     return 64 * k + (nw - 1) * (64 * k - 4)
 
 
-MAX_DIAGONALS = class_capacity(len(CLASSES) - 1)
+MAX_DIAGONALS = class_capacity(10)
 
 
 def class_name(c: int) -> str:
@@ -230,7 +231,7 @@ class Context:
         _check(load_library().ga_context_set_schedule(self._h, SCHEDULES[schedule]), "ga_context_set_schedule")
 
     def set_lanes(self, lanes: int):
-        """Streams (1..3) the persistent launches of one call overlap on."""
+        """Streams (1..4) the persistent launches of one call overlap on."""
         _check(load_library().ga_context_set_lanes(self._h, int(lanes)), "ga_context_set_lanes")
 
     def set_classes(self, classes=None):

@@ -28,10 +28,14 @@
 // The band edges are walls of -inf: the left wall is the DPP fill value of
 // lane 0, the right wall is a slot forced to -inf after each update.
 //
-// Bases are unpacked once per batch from the 2-bit stream (plus N bitmap) to
-// one byte per base (0..3, N = 4). Per 8-step block each slot builds the
-// substitution scores of its next 4 cells with one v_perm_b32 table lookup
-// (4 signed bytes), and each cell adds its byte through an SDWA operand.
+// Bases stay 2-bit packed in HBM (plus the N bitmap). Each wave stages the
+// bases its band covers in two LDS rings (target and query), one byte per
+// base (0..3, N = 4): the ring is filled once when a pair starts and then
+// takes one word (4 bases) per sequence every 8 anti-diagonals, from a word
+// prefetched a block ahead. Per 8-step block each lane reads its byte
+// windows from the rings and each slot builds the substitution scores of its
+// next 4 cells with one v_perm_b32 table lookup (4 signed bytes); each cell
+// adds its byte through an SDWA operand.
 
 #include <hip/hip_runtime.h>
 
@@ -48,21 +52,20 @@ constexpr int NEG_MAX = -(1 << 30) - (1 << 29);  // below every reachable value
 // Every finite score in the frame lies above LIVE_MIN (the range guard keeps
 // them within +-2^29); -inf values, even after their drift, lie below it.
 constexpr int LIVE_MIN = -(1 << 29) - (1 << 27);
-constexpr int PADB = 64;                         // guard bytes around the unpacked streams
 constexpr int WAVE = 64;
 
 // Slot classes: K slots per lane and NW waves per pair hold the band's
 // D <= class_cap diagonals (64*K on one wave, less 4 per extra wave for the
 // shared ghost diagonals); a pair goes to the first class that holds it.
-constexpr int NCLASS = 11;
+constexpr int NCLASS = 12;
 // (K, NW, window) = (4,1,fixed) (8,1,fixed) (16,1,fixed) (24,1,fixed)
 // (32,1,fixed) (8,1,sliding) (16,1,sliding) (24,2,fixed) (32,2,fixed)
-// (32,3,fixed) (32,4,fixed)
+// (32,3,fixed) (32,4,fixed) (4,1,sliding)
 __host__ __device__ constexpr int class_k(int c) {
-    return c == 0 ? 4 : (c == 1 || c == 5) ? 8 : (c == 2 || c == 6) ? 16 : (c == 3 || c == 7) ? 24 : 32;
+    return (c == 0 || c == 11) ? 4 : (c == 1 || c == 5) ? 8 : (c == 2 || c == 6) ? 16 : (c == 3 || c == 7) ? 24 : 32;
 }
-__host__ __device__ constexpr int class_nw(int c) { return c < 7 ? 1 : c < 9 ? 2 : c == 9 ? 3 : 4; }
-__host__ __device__ constexpr bool class_slides(int c) { return c == 5 || c == 6; }
+__host__ __device__ constexpr int class_nw(int c) { return c < 7 || c == 11 ? 1 : c < 9 ? 2 : c == 9 ? 3 : 4; }
+__host__ __device__ constexpr bool class_slides(int c) { return c == 5 || c == 6 || c == 11; }
 // Neighbouring waves of one pair overlap by 2*HALO diagonals: each holds
 // copies ("ghosts") of the HALO diagonals next to its edge, refreshed from
 // their owner every HALO anti-diagonals, so the waves exchange state and
@@ -87,12 +90,12 @@ constexpr uint32_t ALL_CLASSES = (1u << NCLASS) - 1;
 // sliding class only for a band wider than its window, a class of NW waves
 // only for a band that reaches its last wave.
 // The classes in the order they are tried: cheapest first, four bits per
-// class from the lowest nibble. The default is by slots per lane (4, 8,
-// sliding 8, 16, sliding 16, 24, 32), then the multi-wave classes; an
-// autotuned context replaces it with its measured order.
-constexpr uint64_t DEFAULT_ORDER = 0x0ull | (1ull << 4) | (5ull << 8) | (2ull << 12) | (6ull << 16) |
-                                   (3ull << 20) | (4ull << 24) | (7ull << 28) | (8ull << 32) |
-                                   (9ull << 36) | (10ull << 40);
+// class from the lowest nibble. The default is by slots per lane (4,
+// sliding 4, 8, sliding 8, 16, sliding 16, 24, 32), then the multi-wave
+// classes; an autotuned context replaces it with its measured order.
+constexpr uint64_t DEFAULT_ORDER = 0x0ull | (11ull << 4) | (1ull << 8) | (5ull << 12) | (2ull << 16) |
+                                   (6ull << 20) | (3ull << 24) | (4ull << 28) | (7ull << 32) |
+                                   (8ull << 36) | (9ull << 40) | (10ull << 44);
 
 __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *slide,
                                          uint32_t mask = ALL_CLASSES, uint64_t order = DEFAULT_ORDER) {
@@ -120,6 +123,51 @@ __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *s
         }
     }
     return -1;
+}
+
+// The classes the pairs of a batch (lengths up to max_len, band w) can take
+// under `mask` and `order`, as a bit mask. A pair's band spans at most
+// Dmax = 2 min(w, max_len) + 1 diagonals. A sliding class only takes bands
+// wider than its window, so it is out when Dmax fits the window. A fixed or
+// multi-wave class takes the band widths D it holds (up to its capacity,
+// above its one-wave-fewer reach) that no class before it in the order
+// holds; the holder of D is piecewise constant in D with breaks only where
+// a class's range starts or ends, so trying D = 1 and every range end + 1
+// up to Dmax finds every class some width picks (a sliding class taking a
+// width first can only make this an over-estimate). Host function: the
+// persistent schedule skips the launches no pair can reach.
+inline uint32_t reachable_classes(int64_t max_len, int64_t w, uint32_t mask, uint64_t order) {
+    const int64_t half = w >= 0 && w < max_len ? w : max_len;
+    const int64_t Dmax = 2 * half + 1;
+    uint32_t out = 0;
+    int64_t probe[2 * NCLASS + 1];
+    int np = 0;
+    probe[np++] = 1;
+    for (int c = 0; c < NCLASS; ++c) {
+        if (!((mask >> c) & 1u)) continue;
+        if (class_slides(c)) {
+            if (Dmax > class_cap(c)) out |= 1u << c;
+            continue;
+        }
+        const int K = class_k(c), NW = class_nw(c);
+        const int64_t below = NW > 1 ? WAVE * K + (NW - 2) * wave_stride(K) : 0;
+        if (below + 1 <= Dmax) probe[np++] = below + 1;
+        if (class_cap(c) + 1 <= Dmax) probe[np++] = class_cap(c) + 1;
+    }
+    for (int t = 0; t < np; ++t) {
+        const int64_t D = probe[t];
+        for (int k = 0; k < NCLASS; ++k) {
+            const int c = (int)((order >> (4 * k)) & 0xFull);
+            if (!((mask >> c) & 1u) || class_slides(c)) continue;
+            const int K = class_k(c), NW = class_nw(c);
+            const int64_t below = NW > 1 ? WAVE * K + (NW - 2) * wave_stride(K) : 0;
+            if (D <= class_cap(c) && D > below) {
+                out |= 1u << c;
+                break;
+            }
+        }
+    }
+    return out;
 }
 
 // Work groups of one call: the kernel classes (persistent schedule) or the
@@ -155,8 +203,10 @@ __host__ __device__ inline int bucket_class(int b, int64_t w, uint32_t mask = AL
 // and s' = S + q + 2e (the substitution score with the frame's two-step
 // drift folded in; it is what the byte table holds).
 struct DpArgs {
-    const uint8_t *tb;  // unpacked target bytes; tb[16*off + k] is base k
-    const uint8_t *qb;  // unpacked query bytes
+    const uint32_t *tw;  // target 2-bit stream; base k of pair p: word t_off[p] + k/16
+    const uint32_t *qw;  // query 2-bit stream
+    const uint32_t *tn;  // N bitmaps (one bit per base position of the stream), or null
+    const uint32_t *qn;
     const int64_t *t_off;
     const int64_t *q_off;
     const int32_t *t_len;
@@ -356,9 +406,27 @@ struct Track {
 // several waves per pair the exchange every two anti-diagonals, double
 // buffered: the owned edge diagonals each wave hands its neighbours' ghosts
 // and each wave's maxima.
+// Base staging rings of one wave (one per sequence): the byte of base
+// position x sits at ring[x mod BYTES]. A block's windows span at most
+// 32K + 16 positions of each sequence (every lane's K/2 + 4 bases, aligned
+// to words); the ring is refilled 64 words (256 bases) at a time, one word
+// per lane, whenever the next block's windows reach past what it holds, so
+// it also holds a refill's worth beyond the windows. A lane reads its window
+// as K/8 + 3 words from one ring offset; the ring's first MIRROR words are
+// copied past its end, so such a read never wraps.
+template <int K>
+struct Ring {
+    static constexpr int BYTES = K <= 4 ? 512 : K <= 16 ? 1024 : 2048;
+    static constexpr int WORDS = BYTES / 4;
+    static constexpr int MIRROR = K / 8 + 2;
+    static_assert(WORDS >= 8 * K + 4 + WAVE, "a block's windows and one refill must fit the ring");
+};
+
 template <int K, int NW>
 struct PairLds {
     int park[K * WAVE];  // park[s * 64 + lane] = A of slot s
+    // each wave's staged bases: [wave][0 target, 1 query]
+    uint32_t ring[NW][2][Ring<K>::WORDS + Ring<K>::MIRROR];
     // several waves (double-buffered by exchange): the owned edge diagonals
     // a wave hands its neighbours (A, E, X, F, Y of two slots each way) and
     // the wave maxima of the exchange's two anti-diagonals
@@ -841,8 +909,9 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
 }
 
 // Raw words holding the block's base windows T[I0 .. I0+K/2+4) and
-// Q[J0-K/2+1 .. J0+4) of this lane; starts are clamped so the loads stay
-// inside the guarded streams (a clamped lane has no interior cell there).
+// Q[J0-K/2+1 .. J0+4) of this lane, read from the wave's rings. Positions
+// outside a sequence read whatever the ring holds there; they only feed
+// cells outside the rectangle, which never reach an interior cell.
 template <int K>
 struct Windows {
     static constexpr int NW = K / 8 + 3;
@@ -851,15 +920,14 @@ struct Windows {
 };
 
 template <int K>
-__device__ __forceinline__ void load_windows(Windows<K> &wd, const uint8_t *tbase, const uint8_t *qbase,
-                                             int n, int m, int r0, int d0) {
+__device__ __forceinline__ void load_windows(Windows<K> &wd, const uint32_t *ring_t, const uint32_t *ring_q,
+                                             int r0, int d0) {
     constexpr int KH = K / 2;
-    const int I0 = (r0 + d0) >> 1;
-    const int J0 = (r0 - d0) >> 1;
-    const int ts = min(max(I0, -(KH + 4)), n - 1);
-    const int qs = min(max(J0 - KH + 1, -(KH + 3)), m - 1);
-    const uint32_t *tw = reinterpret_cast<const uint32_t *>(tbase + (ts - (ts & 3)));
-    const uint32_t *qw = reinterpret_cast<const uint32_t *>(qbase + (qs - (qs & 3)));
+    constexpr int MASK = Ring<K>::WORDS - 1;
+    const int ts = (r0 + d0) >> 1;           // I0
+    const int qs = ((r0 - d0) >> 1) - KH + 1;  // J0 - K/2 + 1
+    const uint32_t *tw = ring_t + ((ts >> 2) & MASK);
+    const uint32_t *qw = ring_q + ((qs >> 2) & MASK);
 #pragma unroll
     for (int k = 0; k < Windows<K>::NW; ++k) {
         wd.RT[k] = tw[k];
@@ -867,6 +935,66 @@ __device__ __forceinline__ void load_windows(Windows<K> &wd, const uint8_t *tbas
     }
     wd.to = ts & 3;
     wd.qo = qs & 3;
+}
+
+// Four 2-bit codes (bits 0..7) and their N bits (bits 0..3) -> four bytes
+// (0..3, N = 4): the codes spread to byte lanes in two shift-or-mask steps,
+// the N bits by one multiply whose four shifted copies never overlap.
+__device__ __forceinline__ uint32_t expand4(uint32_t c8, uint32_t n4) {
+    const uint32_t y = (c8 | (c8 << 12)) & 0x000F000Fu;
+    const uint32_t codes = (y | (y << 6)) & 0x03030303u;
+    return codes | (((n4 * 0x00204081u) & 0x01010101u) << 2);
+}
+
+// Make the ring of one sequence (2-bit words from word `off` of `words`,
+// N bitmap `nmask` of the whole stream or null, `len` bases) hold the ring
+// words [wlo, whi) (word x = positions 4x .. 4x+3). The ring holds the words
+// below `filled` (wave-uniform); when the block needs more, lanes fill the
+// next 64 words at once, one each (bases past the sequence are left as they
+// are), until it holds enough. Rare: once every 64 words of advance.
+template <int K>
+__device__ __forceinline__ void refill(uint32_t *ring, const uint32_t *words, const uint32_t *nmask, int64_t off,
+                                       int len, int &filled, int wlo, int whi, int lane) {
+    constexpr int WORDS = Ring<K>::WORDS, MIRROR = Ring<K>::MIRROR;
+    if (filled < wlo) filled = wlo;  // nothing below the windows is needed
+    const int wend = (len + 3) >> 2;
+    do {
+        const int x = filled + lane;
+        if (x < wend) {
+            const uint32_t w = words[off + (x >> 2)];
+            uint32_t n4 = 0;
+            if (nmask) {
+                const int64_t bit = 16 * off + 4 * (int64_t)x;
+                n4 = (nmask[bit >> 5] >> (int)(bit & 31)) & 0xFu;
+            }
+            const uint32_t v = expand4((w >> (8 * (x & 3))) & 0xFFu, n4);
+            const int i = x & (WORDS - 1);
+            ring[i] = v;
+            if (i < MIRROR) ring[WORDS + i] = v;
+        }
+        filled += WAVE;
+    } while (filled < whi);
+}
+
+// Stage the bases the windows of the block at anti-diagonal r need, for a
+// wave whose lane 0 holds diagonal b first: target positions
+// [I0, I0 + 32K + 4) and query positions [J0 - 32K + 1, J0 + 4) of lane
+// 0's I0, J0, clipped to the sequences. `ft`, `fq`: the rings' watermarks.
+template <int K>
+__device__ __forceinline__ void stage_block(const DpArgs &P, int p, const Geo &g, uint32_t *ring_t,
+                                            uint32_t *ring_q, int &ft, int &fq, int r, int b, int lane) {
+    const int I0 = (r + b) >> 1, J0 = (r - b) >> 1;
+    {
+        const int lo = max(I0, 0), hi = min(I0 + 32 * K + 4, g.n);
+        if (lo < hi && ((hi + 3) >> 2) > ft)
+            refill<K>(ring_t, P.tw, P.tn, P.t_off[p], g.n, ft, lo >> 2, (hi + 3) >> 2, lane);
+    }
+    {
+        const int lo = max(J0 - 32 * K + 1, 0), hi = min(J0 + 4, g.m);
+        if (lo < hi && ((hi + 3) >> 2) > fq)
+            refill<K>(ring_q, P.qw, P.qn, P.q_off[p], g.m, fq, lo >> 2, (hi + 3) >> 2, lane);
+    }
+    __builtin_amdgcn_wave_barrier();  // the ring writes precede the window reads
 }
 
 // v_bitop3 truth table of (x, y, m) -> m ? (x | y) : (x ^ y), built the way
@@ -1021,10 +1149,12 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     }
     Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false};
 
-    const uint8_t *tbase = P.tb + 16 * P.t_off[p];
-    const uint8_t *qbase = P.qb + 16 * P.q_off[p];
+    // this wave's base rings, filled for the first block
+    uint32_t *ring_t = S.ring[wv][0], *ring_q = S.ring[wv][1];
+    int ft = -(1 << 30), fq = -(1 << 30);
+    stage_block<K>(P, p, g, ring_t, ring_q, ft, fq, r0, g.a0w, lane);
     Windows<K> wd;
-    load_windows<K>(wd, tbase, qbase, n, m, r0, d0);
+    load_windows<K>(wd, ring_t, ring_q, r0, d0);
     int base_next = g.a0w;
     for (;;) {
         if (slide != 0 && base_next != g.a0w) {
@@ -1037,7 +1167,8 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         }
         build_scores<K>(st, wd, P);
         base_next = slide != 0 ? window_base<K>(g, slide, g.a0w, r0 + 8) : g.a0w;
-        load_windows<K>(wd, tbase, qbase, n, m, r0 + 8, base_next + lane * K);  // next block, in flight
+        stage_block<K>(P, p, g, ring_t, ring_q, ft, fq, r0 + 8, base_next, lane);
+        load_windows<K>(wd, ring_t, ring_q, r0 + 8, base_next + lane * K);  // next block, in flight
         bool done;
         if constexpr (NW == 1)
             done = run_block1<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, S);
@@ -1138,37 +1269,6 @@ __global__ __launch_bounds__(256) void ga_valu_probe(int32_t iters, int32_t *sin
 __global__ void ga_zero_i32(int32_t *x, int64_t n) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0;
-}
-
-// 2-bit words (+ N bitmap) -> one byte per base (0..3, N = 4). Thread per
-// word; the PADB guard bytes on both sides are filled with N.
-__global__ void ga_unpack(const uint32_t *words, const uint32_t *nmask, int64_t nwords,
-                          uint8_t *bytes /* points at the leading guard */) {
-    const int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (wi < nwords) {
-        const uint32_t wd = words[wi];
-        uint32_t nb = 0;
-        if (nmask) nb = (nmask[wi >> 1] >> (16 * (wi & 1))) & 0xffffu;
-        uint32_t o[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t v = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int k = 4 * q + b;
-                const uint32_t c = ((nb >> k) & 1u) ? 4u : ((wd >> (2 * k)) & 3u);
-                v |= c << (8 * b);
-            }
-            o[q] = v;
-        }
-        uint4 *dst = reinterpret_cast<uint4 *>(bytes + PADB + 16 * wi);
-        *dst = make_uint4(o[0], o[1], o[2], o[3]);
-    }
-    if (wi < 2 * PADB / 4) {  // guard words
-        uint32_t *g = reinterpret_cast<uint32_t *>(bytes);
-        const int64_t gw = wi < PADB / 4 ? wi : (PADB + 16 * nwords) / 4 + (wi - PADB / 4);
-        g[gw] = 0x04040404u;
-    }
 }
 
 // Work planning. A wave's time on a pair is proportional to the number of
@@ -1449,17 +1549,20 @@ __global__ void ga_probe_fill(int64_t n_pairs, int32_t n, int32_t m, uint32_t *t
 // Stage events of a timed call: start, end of planning, then a start and
 // an end per launch (recorded on the stream the launch runs on).
 constexpr int NEVENTS = 2 + 2 * NGROUP;
-// The persistent launches run on up to three streams at once (the caller's
-// and two of the context's), joined back into the caller's stream; the
-// lane of each class is fixed so the heavy classes of a mixed batch (K=24,
-// sliding K=8, K=4, K=16) land on different streams. The multi-wave
-// classes launch first, so their launches, usually empty, end at once
-// instead of waiting behind a full grid of another class for the resources
-// of their wide workgroups; then the one-wave classes in class order.
-constexpr int MAX_LANES = 3;
-constexpr int LANE_OF[NCLASS] = {0, 2, 1, 0, 1, 1, 2, 1, 0, 2, 0};
-constexpr int FIRST_MULTIWAVE = 7;  // classes 7 .. NCLASS-1 run several waves per pair
-static_assert(class_nw(FIRST_MULTIWAVE - 1) == 1 && class_nw(FIRST_MULTIWAVE) > 1, "multi-wave classes last");
+// The persistent launches run on up to four streams at once (the caller's
+// and three of the context's), joined back into the caller's stream. A
+// launch holds its stream until its last pair ends, so the class holding
+// the band's full width (2w + 1 diagonals, where the longest pairs of a
+// batch land) launches first, on lane 0, ahead of everything: its longest
+// pairs start at once and nothing waits behind them. The other classes
+// spread over lanes 1-3 so the heavy classes of a mixed batch (sliding K=4
+// and K=8, K=4, K=16) land on different streams, the multi-wave classes
+// first on each (usually empty, they end at once instead of waiting behind
+// a full grid of another class for the resources of their wide
+// workgroups).
+constexpr int MAX_LANES = 4;
+constexpr int LANE_OF[NCLASS] = {3, 2, 3, 0, 1, 2, 3, 1, 2, 3, 3, 1};
+constexpr int LAUNCH_ORDER[NCLASS] = {10, 9, 8, 7, 0, 1, 2, 3, 4, 5, 6, 11};
 
 struct ga_context {
     int device;
@@ -1535,7 +1638,8 @@ void launch_class(int c, const DpArgs &a, int grid, hipStream_t s) {
     case 7: launch_dp<24, 2, false>(a, grid, s); break;
     case 8: launch_dp<32, 2, false>(a, grid, s); break;
     case 9: launch_dp<32, 3, false>(a, grid, s); break;
-    default: launch_dp<32, 4, false>(a, grid, s); break;
+    case 10: launch_dp<32, 4, false>(a, grid, s); break;
+    default: launch_dp<4, 1, true>(a, grid, s); break;
     }
 }
 
@@ -1594,6 +1698,7 @@ int ga_context_create(ga_context_t **out, int device) {
     ctx->blocks_per_cu[8] = blocks_per_cu<32, 2, false>();
     ctx->blocks_per_cu[9] = blocks_per_cu<32, 3, false>();
     ctx->blocks_per_cu[10] = blocks_per_cu<32, 4, false>();
+    ctx->blocks_per_cu[11] = blocks_per_cu<4, 1, true>();
     if (hipMalloc(&ctx->d_err, sizeof(int32_t)) != hipSuccess) {
         (void)hipGetLastError();
         free(ctx);
@@ -1936,17 +2041,11 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     const size_t off_cursor = off_hist + sizeof(int32_t) * PLAN_BINS;
     const size_t off_keys = off_cursor + sizeof(int32_t) * PLAN_BINS;
     const size_t off_lists = align_up(off_keys + sizeof(int32_t) * (size_t)np, 256);
-    const size_t off_tb = align_up(off_lists + sizeof(int32_t) * (size_t)np, 256);
-    const size_t tb_size = align_up(16 * (size_t)bt->t_nwords + 2 * PADB, 256);
-    const size_t off_qb = off_tb + tb_size;
-    const size_t qb_size = align_up(16 * (size_t)bt->q_nwords + 2 * PADB, 256);
-    const int rc = ensure_ws(ctx, off_qb + qb_size);
+    const int rc = ensure_ws(ctx, off_lists + sizeof(int32_t) * (size_t)np);
     if (rc != GA_OK) return rc;
     char *ws = (char *)ctx->ws;
     int32_t *counters = (int32_t *)(ws + off_cnt);
     int32_t *lists = (int32_t *)(ws + off_lists);
-    uint8_t *tb = (uint8_t *)(ws + off_tb);
-    uint8_t *qb = (uint8_t *)(ws + off_qb);
     const int TB = 256;
     const bool timed = ctx->timing != 0;
     ctx->timed_last = timed ? 1 : 0;
@@ -1954,16 +2053,6 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     // counters and the bucket histogram are contiguous: one fill clears both
     hipLaunchKernelGGL(ga_zero_i32, dim3((unsigned)((off_cursor / 4 + TB - 1) / TB)), dim3(TB), 0, s,
                        counters, (int64_t)(off_cursor / 4));
-    {
-        const int64_t nthr = bt->t_nwords > 2 * PADB / 4 ? bt->t_nwords : 2 * PADB / 4;
-        hipLaunchKernelGGL(ga_unpack, dim3((unsigned)((nthr + TB - 1) / TB)), dim3(TB), 0, s, bt->t_words_dev,
-                           bt->t_nmask_dev, bt->t_nwords, tb);
-    }
-    {
-        const int64_t nthr = bt->q_nwords > 2 * PADB / 4 ? bt->q_nwords : 2 * PADB / 4;
-        hipLaunchKernelGGL(ga_unpack, dim3((unsigned)((nthr + TB - 1) / TB)), dim3(TB), 0, s, bt->q_words_dev,
-                           bt->q_nmask_dev, bt->q_nwords, qb);
-    }
     PlanArgs pa;
     pa.n_pairs = np;
     pa.t_off = bt->t_off_dev;
@@ -1991,8 +2080,10 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     if (timed) hipEventRecord(ctx->ev[1], s);
 
     DpArgs da;
-    da.tb = tb + PADB;
-    da.qb = qb + PADB;
+    da.tw = bt->t_words_dev;
+    da.qw = bt->q_words_dev;
+    da.tn = bt->t_nmask_dev;
+    da.qn = bt->q_nmask_dev;
     da.t_off = bt->t_off_dev;
     da.q_off = bt->q_off_dev;
     da.t_len = bt->t_len_dev;
@@ -2049,7 +2140,7 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         // its lane, join them back: the classes' launches overlap, so the
         // tail of one (its last long pairs) runs beside the others
         const int L = ctx->lanes;
-        hipStream_t lane_s[MAX_LANES] = {s, s, s};
+        hipStream_t lane_s[MAX_LANES] = {s, s, s, s};
         if (L > 1) {
             if (!ctx->fork_ev) {
                 if (hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess) {
@@ -2067,15 +2158,15 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
                 lane_s[k] = ctx->side[k - 1];
             }
         }
-        for (int k = 0; k < NCLASS; ++k) {
-            // the multi-wave classes first (widest first), then the others
-            // in class order
-            const int nmw = NCLASS - FIRST_MULTIWAVE;
-            const int c = k < nmw ? NCLASS - 1 - k : k - nmw;
-            if (!((ctx->class_mask >> c) & 1u)) continue;
+        int slide;
+        const int full = class_for(bt->max_len, bt->max_len, w, &slide, ctx->class_mask, ctx->class_order);
+        const uint32_t reach = reachable_classes(bt->max_len, w, ctx->class_mask, ctx->class_order);
+        for (int k = -1; k < NCLASS; ++k) {
+            const int c = k < 0 ? full : LAUNCH_ORDER[k];
+            if (c < 0 || (k >= 0 && c == full) || !((reach >> c) & 1u)) continue;
             const int64_t want = (int64_t)ctx->num_cu * ctx->blocks_per_cu[c];
             const int grid = (int)(np < want ? np : want);
-            hipStream_t ls = lane_s[LANE_OF[c] % L];
+            hipStream_t ls = lane_s[k < 0 ? 0 : LANE_OF[c] % L];
             da.group = c;
             if (timed) hipEventRecord(ctx->ev[2 + 2 * nl], ls);
             launch_class(c, da, grid, ls);

@@ -466,8 +466,9 @@ def test_sliding_window_short_by_long(w):
             T.append(base)
             Q.append(short)
     # short sides exactly at and one past each sliding window's limit
-    # (2s + 11 + K <= 64K: s <= 246 for K=8, s <= 498 for K=16), both ways
-    for s in (246, 247, 498, 499):
+    # (2s + 11 + K <= 64K: s <= 120 for K=4, s <= 246 for K=8, s <= 498 for
+    # K=16), both ways
+    for s in (120, 121, 246, 247, 498, 499):
         base = seq(b"ACGT", int(rng.integers(3000, 4000)))
         short = base[100:100 + s]
         T += [short, base]
@@ -477,7 +478,7 @@ def test_sliding_window_short_by_long(w):
         cls = [ga.ga_pair_class(int(n), int(m), w) for n, m in zip(b.t_len, b.q_len)]
         _say(f"sliding w={w} Z={Z}: classes {sorted(set(cls))}")
         if w < 0 or w >= 300:
-            assert {5, 6} & set(cls)
+            assert {5, 6} & set(cls) and 11 in cls
         want, _ = oracle_align(b)
         assert_same(gpu_align(b), want, b, f"sliding w={w} Z={Z}")
 
@@ -567,6 +568,7 @@ def test_every_class_same_results():
         ("w=1500", seqgen.random_pairs(rng, 8, 3200, 3500, err=0.05, w=1500, zdrop=400), [7, 8]),
         ("w=2500", seqgen.random_pairs(rng, 4, 2700, 3000, err=0.05, w=2500, zdrop=400), [9]),
         ("w=3500", seqgen.random_pairs(rng, 3, 3600, 3800, err=0.05, w=3500, zdrop=400), [10]),
+        ("sliding K4", _short_by_long(rng, 16, 1500, 2500, 20, 115, 751), [11, 5, 2, 3, 4]),
     ]
     ctx = ga.Context(0)
     for label, b, classes in scenarios:
@@ -740,8 +742,8 @@ def test_autotune_order_and_results():
 
 
 def test_lanes_same_results():
-    """Spreading the class launches over one, two or three streams gives the
-    same results (checked against the oracle on a mixed sample)."""
+    """Spreading the class launches over one to four streams gives the same
+    results (checked against the oracle on a mixed sample)."""
     import torch
 
     import paper_2403_06478_amd as ga
@@ -750,10 +752,10 @@ def test_lanes_same_results():
     ctx = ga.Context(0)
     lib = ga.load_library()
     assert lib.ga_context_set_lanes(ctx._h, 0) == ga.GA_EINVAL
-    assert lib.ga_context_set_lanes(ctx._h, 4) == ga.GA_EINVAL
+    assert lib.ga_context_set_lanes(ctx._h, 5) == ga.GA_EINVAL
     packed = ga.pack_batch(ctx, b)
     outs = []
-    for lanes in (1, 2, 3):
+    for lanes in (1, 2, 3, 4):
         ctx.set_lanes(lanes)
         ctx.set_timing(True)
         out = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
@@ -763,9 +765,9 @@ def test_lanes_same_results():
         assert all(x >= 0 for x in ms) and sum(ms[1:]) > 0
         outs.append(out.cpu().numpy())
         _say(f"lanes {lanes}: {b.n_pairs} pairs, stages {[round(x, 3) for x in ms]}")
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
     want, _ = oracle_align(b)
-    assert_same(outs[2], want, b, "lanes")
+    assert_same(outs[-1], want, b, "lanes")
     ctx.close()
 
 
