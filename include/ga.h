@@ -143,6 +143,23 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_
  * shapes once before capturing. The graph then holds the pointers, sizes
  * and parameters of the captured call; pairs of length 0 finish at once. */
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * ga_align_batch, with the same arguments and results, but the call's
+ * planning workspace is a fixed device array inside the library (about
+ * 9 MiB, one copy per GPU, held until the process ends) instead of the
+ * context's workspace, and the call allocates nothing. It takes at most
+ * GA_NOALLOC_MAX_PAIRS pairs (GA_EINVAL above that) and the persistent or
+ * unordered schedule (GA_EUNSUPPORTED under GA_SCHED_BUCKETED, which waits
+ * for the host). Every such call on one GPU, from any context, uses that
+ * GPU's one array: calls that overlap on the device race, so order them
+ * (one stream, or the caller's synchronisation). Each call clears what it
+ * needs first. GA_EHIP if the array could not be located on the device when
+ * the context was created. */
+#define GA_NOALLOC_MAX_PAIRS (1 << 20)
+int ga_align_batch_noalloc(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
+                           int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);
+
 /* Work schedules of ga_align_batch (results are identical under both):
  * GA_SCHED_PERSISTENT (the default): every pair goes to the cheapest kernel
  * class that runs it, ordered longest first within the class, and each

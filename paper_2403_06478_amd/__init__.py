@@ -34,7 +34,8 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_calibrate_valu", "ga_context_set_schedule", "ga_context_set_classes",
                "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class", "ga_context_set_lanes",
                "ga_host_device_pointer", "ga_server_create", "ga_server_destroy", "ga_server_submit",
-               "ga_server_poll", "ga_server_pending", "ga_server_batches", "ga_server_replay")
+               "ga_server_poll", "ga_server_pending", "ga_server_batches", "ga_server_replay",
+               "ga_align_batch_noalloc")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
@@ -126,6 +127,8 @@ def load_library() -> ctypes.CDLL:
     lib.ga_pack.restype = ctypes.c_int
     lib.ga_align_batch.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), i32, i32, vp, vp]
     lib.ga_align_batch.restype = ctypes.c_int
+    lib.ga_align_batch_noalloc.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), i32, i32, vp, vp]
+    lib.ga_align_batch_noalloc.restype = ctypes.c_int
     lib.ga_count_cells.argtypes = [i32, i32, i32, i32]
     lib.ga_count_cells.restype = i64
     lib.ga_context_set_timing.argtypes = [vp, ctypes.c_int]
@@ -352,6 +355,21 @@ def ga_align_batch(ctx: Context, packed: PackedBatch, scoring: dict, w: int, Z: 
     _check(lib.ga_align_batch(ctx.handle, ctypes.byref(b), ctypes.byref(sc), int(w), int(Z),
                               out.data_ptr(), _stream_handle(stream)), "ga_align_batch")
     return out[:packed.n_pairs]
+
+
+def ga_align_batch_noalloc(ctx: Context, packed: PackedBatch, scoring: dict, w: int, Z: int, out,
+                           stream=None):
+    """As ``ga_align_batch`` through the allocation-free entry point: fills
+    the caller's device int32 tensor ``out`` [>= n_pairs, 7]."""
+    lib = load_library()
+    b = packed.struct()
+    sc = scoring_struct(scoring)
+    _check(lib.ga_align_batch_noalloc(ctx.handle, ctypes.byref(b), ctypes.byref(sc), int(w), int(Z),
+                                      out.data_ptr(), _stream_handle(stream)), "ga_align_batch_noalloc")
+    return out[:packed.n_pairs]
+
+
+NOALLOC_MAX_PAIRS = 1 << 20
 
 
 def ga_pair_class(n: int, m: int, w: int) -> int:

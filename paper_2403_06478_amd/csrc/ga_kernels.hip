@@ -43,6 +43,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "ga.h"
 
 namespace {
@@ -1542,9 +1544,31 @@ __global__ void ga_probe_fill(int64_t n_pairs, int32_t n, int32_t m, uint32_t *t
     }
 }
 
+// Layout of one call's planning workspace for n pairs: the counters, the
+// histogram and cursors of the cost buckets (cleared or written by the
+// planning kernels on every call), one key and one list entry per pair.
+constexpr size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t WS_HIST = round_up(sizeof(int32_t) * CNT_WORDS, 256);
+constexpr size_t WS_CURSOR = WS_HIST + sizeof(int32_t) * PLAN_BINS;
+constexpr size_t WS_KEYS = WS_CURSOR + sizeof(int32_t) * PLAN_BINS;
+constexpr size_t ws_lists(size_t n) { return round_up(WS_KEYS + sizeof(int32_t) * n, 256); }
+constexpr size_t ws_bytes(size_t n) { return ws_lists(n) + sizeof(int32_t) * n; }
+
 }  // namespace
 
 // --------------------------------------------------------------- host side
+
+// The allocation-free entry point's workspace (ga_align_batch_noalloc): one
+// call's planning workspace for up to GA_NOALLOC_MAX_PAIRS pairs (about
+// 9 MiB), a file-scope device array of which each GPU holds its own copy
+// until the process ends. Host code never uses the array's name as an
+// address: ga_context_create looks up this device's copy once
+// (hipGetSymbolAddress, with the device current) and every later use goes
+// through that pointer.
+static __device__ __align__(256) unsigned char scratch[ws_bytes(GA_NOALLOC_MAX_PAIRS)];
+constexpr int SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[SCRATCH_DEVICES];  // this device's copy of `scratch`, once looked up
 
 // Stage events of a timed call: start, end of planning, then a start and
 // an end per launch (recorded on the stream the launch runs on).
@@ -1584,6 +1608,7 @@ struct ga_context {
     int launch_class[NGROUP];       // their kernel classes
     int32_t *h_counts;              // pinned host copy of the group sizes (bucketed schedule)
     hipEvent_t ev[NEVENTS];
+    void *scratch;                  // this device's copy of `scratch` (null: not available)
 };
 
 namespace {
@@ -1708,6 +1733,30 @@ int ga_context_create(ga_context_t **out, int device) {
         hipFree(ctx->d_err);
         free(ctx);
         return GA_EHIP;
+    }
+    // the side streams and their fork/join events, made now so that no
+    // alignment call creates anything
+    bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < MAX_LANES - 1; ++k)
+        ok = hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        ga_context_destroy(ctx);
+        return GA_EHIP;
+    }
+    // this device's copy of the allocation-free entry point's scratch
+    if (device < SCRATCH_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[device]) {
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+                (void)hipGetLastError();
+                ptr = nullptr;
+            }
+            g_scratch_dev[device] = ptr;
+        }
+        ctx->scratch = g_scratch_dev[device];
     }
     *out = ctx;
     return GA_OK;
@@ -2004,8 +2053,13 @@ int64_t ga_count_cells(int32_t n, int32_t m, int32_t w, int32_t r_end) {
     return total;
 }
 
-int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w, int32_t Z,
-                   ga_result_t *out_dev, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Host validation of an alignment call (GA_OK, GA_EINVAL or GA_EUNSUPPORTED).
+int validate_call(const ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w, int32_t Z,
+                  const ga_result_t *out_dev) {
     if (!ctx || !bt || !sc || bt->n_pairs < 0) return GA_EINVAL;
     if (bt->n_pairs == 0) return GA_OK;
     if (!out_dev || !bt->t_off_dev || !bt->q_off_dev || !bt->t_len_dev || !bt->q_len_dev) return GA_EINVAL;
@@ -2033,19 +2087,18 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         const int64_t wl = w < 0 ? bt->max_len : (w < bt->max_len ? w : bt->max_len);
         if (2 * wl + 1 > MAX_DIAGONALS) return GA_EUNSUPPORTED;
     }
-    SetDevice sd(ctx->device);
-    hipStream_t s = (hipStream_t)stream;
+    return GA_OK;
+}
+
+// The planning and alignment launches of one validated, non-empty call on
+// the device current, with `ws` the call's planning workspace
+// (ws_bytes(n_pairs) bytes of device memory).
+int align_launch(ga_context *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w, int32_t Z,
+                 ga_result_t *out_dev, hipStream_t s, char *ws) {
     const int64_t np = bt->n_pairs;
-    const size_t off_cnt = 0;
-    const size_t off_hist = align_up(sizeof(int32_t) * CNT_WORDS, 256);
-    const size_t off_cursor = off_hist + sizeof(int32_t) * PLAN_BINS;
-    const size_t off_keys = off_cursor + sizeof(int32_t) * PLAN_BINS;
-    const size_t off_lists = align_up(off_keys + sizeof(int32_t) * (size_t)np, 256);
-    const int rc = ensure_ws(ctx, off_lists + sizeof(int32_t) * (size_t)np);
-    if (rc != GA_OK) return rc;
-    char *ws = (char *)ctx->ws;
-    int32_t *counters = (int32_t *)(ws + off_cnt);
-    int32_t *lists = (int32_t *)(ws + off_lists);
+    const size_t off_cursor = WS_CURSOR;
+    int32_t *counters = (int32_t *)ws;
+    int32_t *lists = (int32_t *)(ws + ws_lists((size_t)np));
     const int TB = 256;
     const bool timed = ctx->timing != 0;
     ctx->timed_last = timed ? 1 : 0;
@@ -2068,9 +2121,9 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     pa.mask = ctx->class_mask;
     pa.order = ctx->class_order;
     pa.counters = counters;
-    pa.hist = (int32_t *)(ws + off_hist);
-    pa.cursor = (int32_t *)(ws + off_cursor);
-    pa.keys = (int32_t *)(ws + off_keys);
+    pa.hist = (int32_t *)(ws + WS_HIST);
+    pa.cursor = (int32_t *)(ws + WS_CURSOR);
+    pa.keys = (int32_t *)(ws + WS_KEYS);
     pa.lists = lists;
     pa.err = ctx->d_err;
     pa.out = out_dev;
@@ -2142,16 +2195,6 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
         const int L = ctx->lanes;
         hipStream_t lane_s[MAX_LANES] = {s, s, s, s};
         if (L > 1) {
-            if (!ctx->fork_ev) {
-                if (hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess) {
-                    ctx->fork_ev = nullptr;
-                    return GA_EHIP;
-                }
-                for (int k = 0; k < MAX_LANES - 1; ++k)
-                    if (hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking) != hipSuccess ||
-                        hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming) != hipSuccess)
-                        return GA_EHIP;
-            }
             if (hipEventRecord(ctx->fork_ev, s) != hipSuccess) return GA_EHIP;
             for (int k = 1; k < L; ++k) {
                 if (hipStreamWaitEvent(ctx->side[k - 1], ctx->fork_ev, 0) != hipSuccess) return GA_EHIP;
@@ -2182,6 +2225,31 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     }
     ctx->n_launch_last = nl;
     return hipGetLastError() == hipSuccess ? GA_OK : GA_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w, int32_t Z,
+                   ga_result_t *out_dev, void *stream) {
+    int rc = validate_call(ctx, bt, sc, w, Z, out_dev);
+    if (rc != GA_OK || bt->n_pairs == 0) return rc;
+    SetDevice sd(ctx->device);
+    rc = ensure_ws(ctx, ws_bytes((size_t)bt->n_pairs));
+    if (rc != GA_OK) return rc;
+    return align_launch(ctx, bt, sc, w, Z, out_dev, (hipStream_t)stream, (char *)ctx->ws);
+}
+
+int ga_align_batch_noalloc(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w,
+                           int32_t Z, ga_result_t *out_dev, void *stream) {
+    int rc = validate_call(ctx, bt, sc, w, Z, out_dev);
+    if (rc != GA_OK || bt->n_pairs == 0) return rc;
+    if (bt->n_pairs > GA_NOALLOC_MAX_PAIRS) return GA_EINVAL;
+    if (ctx->schedule == GA_SCHED_BUCKETED) return GA_EUNSUPPORTED;  // it waits for the host
+    if (!ctx->scratch) return GA_EHIP;
+    SetDevice sd(ctx->device);
+    return align_launch(ctx, bt, sc, w, Z, out_dev, (hipStream_t)stream, (char *)ctx->scratch);
 }
 
 }  // extern "C"
