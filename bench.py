@@ -83,31 +83,110 @@ def read_traffic(kernel: str, workload: str):
     return float(m.group(1)) if m else None
 
 
+def cpu_threads():
+    """Host threads for the oracle baseline: every CPU this process may run
+    on, capped at the CPU share the job was given (OMP_NUM_THREADS, when
+    set). Returns (threads, CPUs the host reports)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS")
+    threads = avail
+    if share and share.isdigit() and int(share) > 0:
+        threads = min(avail, int(share))
+    return max(1, threads), os.cpu_count() or avail
+
+
 def cpu_baseline(batch, n_sample: int):
     import numpy as np
 
     import oracle
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    cores, host_cpus = cpu_threads()
     sub = batch.subset(np.arange(min(n_sample, batch.n_pairs)))
-    log(f"cpu baseline: oracle on {sub.n_pairs} pairs, {cores} threads")
+    oracle.build(force=True, native=True)  # -O3 -march=native for this host
+    log(f"cpu baseline: oracle (-O3 -march=native) on {sub.n_pairs} pairs, {cores} threads "
+        f"({host_cpus} CPUs on the host)")
     t0 = time.perf_counter()
-    _, cells = oracle.align_batch(sub, nthreads=cores)
+    _, cells = oracle.align_batch(sub, nthreads=cores, native=True)
     dt = time.perf_counter() - t0
     # one thread on a sixteenth of the sample (about as long again)
     one = sub.subset(np.arange(max(1, sub.n_pairs // 16)))
     t0 = time.perf_counter()
-    _, cells1 = oracle.align_batch(one, nthreads=1)
+    _, cells1 = oracle.align_batch(one, nthreads=1, native=True)
     dt1 = time.perf_counter() - t0
     return {"value": round(float(cells.sum()) / dt / 1e9, 4), "unit": "GCUPS", "cores": cores,
-            "kind": "oracle",
+            "host_cpus": host_cpus, "kind": "oracle", "build": "gcc -O3 -march=native",
             "sample": f"first {sub.n_pairs} pairs of the benchmark batch "
                       f"({int(cells.sum())} cells, {dt:.1f} s)",
             "one_core": {"value": round(float(cells1.sum()) / dt1 / 1e9, 4),
                          "sample": f"first {one.n_pairs} pairs ({int(cells1.sum())} cells, {dt1:.1f} s)"}}
+
+
+def batching_comparison(ctx, steps: int = 3):
+    """The heavy-tailed 1M-pair mix under the persistent schedule (this
+    context's class order) and the plain per-length-bucket launches: median
+    step time of `steps` timed calls each after one warm-up, GCUPS from the
+    algorithmic cells, and the two schedules' results compared pair by
+    pair."""
+    import numpy as np
+    import torch
+
+    import paper_2403_06478_amd as ga
+    import seqgen
+
+    wid, wdesc = WORKLOADS["mixed"]
+    batch = seqgen.make_workload(wid)
+    packed = ga.pack_batch(ctx, batch)
+    stream = torch.cuda.current_stream()
+    res, ms = {}, {}
+    for sched in ("persistent", "bucketed"):
+        ctx.set_schedule(sched)
+        out = torch.empty((batch.n_pairs, 7), dtype=torch.int32, device="cuda")
+        ga.ga_align_batch(ctx, packed, batch.scoring, batch.w, batch.zdrop, out=out, stream=stream)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ga.ga_align_batch(ctx, packed, batch.scoring, batch.w, batch.zdrop, out=out, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        ctx.check()
+        res[sched] = out.cpu().numpy()
+        ms[sched] = float(np.median(times))
+        log(f"batching: {sched} {[round(t, 2) for t in times]} ms")
+    ctx.set_schedule("persistent")
+    same = bool(np.array_equal(res["persistent"], res["bucketed"]))
+    if not same:
+        raise RuntimeError("persistent and bucketed schedules gave different results on the mix")
+    cells = int(ga.count_cells(batch.t_len, batch.q_len, batch.w, res["persistent"]).sum())
+    del packed
+    torch.cuda.empty_cache()
+    g = {k: cells / (v / 1e3) / 1e9 for k, v in ms.items()}
+    return {"workload": wdesc, "pairs": batch.n_pairs, "cells": cells, "steps": steps,
+            "persistent_ms": round(ms["persistent"], 3), "bucketed_ms": round(ms["bucketed"], 3),
+            "persistent_gcups": round(g["persistent"], 3), "bucketed_gcups": round(g["bucketed"], 3),
+            "speedup": round(ms["bucketed"] / ms["persistent"], 3), "same_results": same,
+            "statistic": "median device time per call (HIP events)"}
+
+
+def serving_summary(duration_s: float):
+    """Serving at 0.5 and 0.8 of the server's saturated throughput (the
+    serving workload, native host loop, captured graphs): p50/p99 per rate
+    for short and long requests, every result checked against the offline
+    batch."""
+    from paper_2403_06478_amd import serve
+
+    lines = serve.serving_benchmark(requests=20000, rates=(0.5, 0.8), duration=duration_s, log=log)
+    keep = ("rate_of_capacity", "qps", "requests", "served_req_per_s", "p50_ms", "p99_ms", "p50_short_ms",
+            "p99_short_ms", "p50_long_ms", "p99_long_ms", "gcups", "same_as_offline")
+    out = {"workload": lines[0]["workload"], "capacity_req_per_s": lines[0]["capacity_req_per_s"],
+           "offline_gcups": lines[0]["offline_gcups"], "saturated_gcups": lines[0]["saturated_gcups"],
+           "duration_s_per_rate": duration_s, "host_loop": lines[0]["host_loop"], "graphs": lines[0]["graphs"],
+           "latency": "arrival to results visible on the host", "rates": [{k: l[k] for k in keep} for l in lines]}
+    return out
 
 
 def main():
@@ -126,6 +205,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-end-to-end", action="store_true",
                     help="skip the end-to-end runs after the timed steps (profiling runs)")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the persistent-vs-bucketed comparison on the 1M-pair mix")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving latency runs")
+    ap.add_argument("--serving-seconds", type=float, default=8.0,
+                    help="seconds of Poisson arrivals per serving rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (scales rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -250,6 +334,15 @@ def main():
     roofline["frac_measured"] = round(achieved / measured_peak, 4)
     log(f"measured int32 VALU peak {measured_peak:.2f} T lane-ops/s")
 
+    batching = None
+    if not args.no_batching:
+        batching = batching_comparison(ctx)
+        log(f"batching: persistent {batching['persistent_gcups']} GCUPS, bucketed "
+            f"{batching['bucketed_gcups']} GCUPS ({batching['speedup']}x)")
+    serving = None
+    if not args.no_serving:
+        serving = serving_summary(args.serving_seconds)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(batch, args.cpu_sample)
@@ -280,6 +373,8 @@ def main():
             "includes": "host ASCII upload (pageable), packing kernel, alignment, results to host"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batching": batching,
+        "serving": serving,
     }
     print(json.dumps(line))
 

@@ -154,7 +154,9 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_
  * for the host). Every such call on one GPU, from any context, uses that
  * GPU's one array: calls that overlap on the device race, so order them
  * (one stream, or the caller's synchronisation). Each call clears what it
- * needs first. GA_EHIP if the array could not be located on the device when
+ * needs first. Its launches spread over the context's streams (see
+ * ga_context_set_lanes) only if an earlier ga_align_batch on the context
+ * made them; otherwise they all run on `stream`. GA_EHIP if the array could not be located on the device when
  * the context was created. */
 #define GA_NOALLOC_MAX_PAIRS (1 << 20)
 int ga_align_batch_noalloc(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,

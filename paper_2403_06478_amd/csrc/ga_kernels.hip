@@ -1734,17 +1734,6 @@ int ga_context_create(ga_context_t **out, int device) {
         free(ctx);
         return GA_EHIP;
     }
-    // the side streams and their fork/join events, made now so that no
-    // alignment call creates anything
-    bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; ok && k < MAX_LANES - 1; ++k)
-        ok = hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming) == hipSuccess;
-    if (!ok) {
-        (void)hipGetLastError();
-        ga_context_destroy(ctx);
-        return GA_EHIP;
-    }
     // this device's copy of the allocation-free entry point's scratch
     if (device < SCRATCH_DEVICES) {
         std::lock_guard<std::mutex> lock(g_scratch_mu);
@@ -2090,9 +2079,37 @@ int validate_call(const ga_context_t *ctx, const ga_batch_t *bt, const ga_scorin
     return GA_OK;
 }
 
+// The context's side streams and their fork/join events, made on first
+// use by an allocating call with more than one lane. (Made only then: a
+// context that never needs them -- a serving slot on one lane -- must not
+// add streams, which would share the GPU's few hardware queues with the
+// streams that matter.)
+int make_side_streams(ga_context *ctx) {
+    if (ctx->fork_ev) return GA_OK;
+    bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < MAX_LANES - 1; ++k)
+        ok = hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
+        ctx->fork_ev = nullptr;
+        for (int k = 0; k < MAX_LANES - 1; ++k) {
+            if (ctx->side[k]) hipStreamDestroy(ctx->side[k]);
+            if (ctx->join_ev[k]) hipEventDestroy(ctx->join_ev[k]);
+            ctx->side[k] = nullptr;
+            ctx->join_ev[k] = nullptr;
+        }
+        return GA_EHIP;
+    }
+    return GA_OK;
+}
+
 // The planning and alignment launches of one validated, non-empty call on
 // the device current, with `ws` the call's planning workspace
-// (ws_bytes(n_pairs) bytes of device memory).
+// (ws_bytes(n_pairs) bytes of device memory). The persistent launches
+// spread over the context's lanes when its side streams exist, else all
+// run on `s`.
 int align_launch(ga_context *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w, int32_t Z,
                  ga_result_t *out_dev, hipStream_t s, char *ws) {
     const int64_t np = bt->n_pairs;
@@ -2192,7 +2209,7 @@ int align_launch(ga_context *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, 
         // fork the context's streams off the caller's, launch each class on
         // its lane, join them back: the classes' launches overlap, so the
         // tail of one (its last long pairs) runs beside the others
-        const int L = ctx->lanes;
+        const int L = ctx->fork_ev ? ctx->lanes : 1;
         hipStream_t lane_s[MAX_LANES] = {s, s, s, s};
         if (L > 1) {
             if (hipEventRecord(ctx->fork_ev, s) != hipSuccess) return GA_EHIP;
@@ -2237,6 +2254,7 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     if (rc != GA_OK || bt->n_pairs == 0) return rc;
     SetDevice sd(ctx->device);
     rc = ensure_ws(ctx, ws_bytes((size_t)bt->n_pairs));
+    if (rc == GA_OK && ctx->lanes > 1 && ctx->schedule != GA_SCHED_BUCKETED) rc = make_side_streams(ctx);
     if (rc != GA_OK) return rc;
     return align_launch(ctx, bt, sc, w, Z, out_dev, (hipStream_t)stream, (char *)ctx->ws);
 }

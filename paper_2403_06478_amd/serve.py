@@ -513,9 +513,69 @@ def offline(batch, device: int = 0, repeats: int = 3):
     return res, dt
 
 
-def main(argv=None):
+def serving_benchmark(requests: int = 20000, rates=(0.5, 0.8), duration=None, seed: int = 0,
+                      python_loop: bool = False, log=None, **server_args):
+    """Offline batch, saturated server and Poisson arrivals at fractions of
+    the saturated throughput over the ``serving`` workload's request pool;
+    returns one dict per rate (latency percentiles, throughput, whether every
+    served result equals the offline batch's). ``duration``: seconds of
+    arrivals per rate, cycling over the pool (default: the pool once)."""
     import seqgen
 
+    say = log or (lambda msg: sys.stderr.write(msg + "\n"))
+    batch = seqgen.make_workload("serving", n_pairs=requests, seed=seed)
+    res_off, dt_off = offline(batch)
+    cells_pool = count_cells(batch.t_len, batch.q_len, batch.w, res_off)
+    cells = int(cells_pool.sum())
+    say(f"[serve] offline: {batch.n_pairs} requests as one batch in {dt_off * 1e3:.1f} ms "
+        f"({batch.n_pairs / dt_off:.0f} req/s, {cells / dt_off / 1e9:.1f} GCUPS)")
+    # the server's own capacity: every request waiting at the start
+    run = serve_trace if python_loop else serve_trace_native
+    res_sat, lat_sat, wall_sat, nb_sat = run(batch, np.zeros(batch.n_pairs), **server_args)
+    capacity = batch.n_pairs / wall_sat
+    say(f"[serve] saturated: {wall_sat * 1e3:.1f} ms, {capacity:.0f} req/s, {nb_sat} batches, "
+        f"{cells / wall_sat / 1e9:.1f} GCUPS")
+    if not np.array_equal(res_sat, res_off):
+        raise RuntimeError("served results differ from the offline batch")
+    long_pool = batch.t_len + batch.q_len > 8000
+    lines = []
+    for frac in rates:
+        qps = frac * capacity
+        rng = np.random.default_rng([5, seed, 1])
+        n_req = batch.n_pairs if duration is None else max(1, int(np.ceil(qps * duration)))
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n_req))
+        pairs = np.arange(n_req) % batch.n_pairs  # request k asks for pool pair k mod pool size
+        res, lat, wall, nb = run(batch, arrivals, pairs=pairs, **server_args)
+        same = bool(np.array_equal(res, res_off[pairs]))
+        long_ = long_pool[pairs]
+        req_cells = int(cells_pool[pairs].sum())
+        line = {
+            "metric": "serving latency", "unit": "ms", "qps": round(qps, 1), "rate_of_capacity": frac,
+            "capacity_req_per_s": round(capacity, 1), "requests": n_req, "pool": batch.n_pairs,
+            "served_req_per_s": round(n_req / wall, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "p50_short_ms": round(float(np.percentile(lat[~long_], 50)) * 1e3, 3),
+            "p99_short_ms": round(float(np.percentile(lat[~long_], 99)) * 1e3, 3),
+            "p50_long_ms": round(float(np.percentile(lat[long_], 50)) * 1e3, 3) if long_.any() else None,
+            "p99_long_ms": round(float(np.percentile(lat[long_], 99)) * 1e3, 3) if long_.any() else None,
+            "gcups": round(req_cells / wall / 1e9, 3), "offline_gcups": round(cells / dt_off / 1e9, 3),
+            "saturated_gcups": round(cells / wall_sat / 1e9, 3),
+            "batches": nb, "wall_s": round(wall, 3), "same_as_offline": same,
+            "graphs": bool(server_args.get("graphs", True)),
+            "host_loop": "python" if python_loop else "native",
+            "workload": "seqgen serving workload: 95% pairs of 100-1000 bp (5% errors), 5% of 10-25 kb "
+                        "(1% errors + indels), w=500, Z=400, Poisson arrivals",
+        }
+        say(f"[serve] rate {frac}: {n_req} requests, p50 {line['p50_ms']} ms, p99 {line['p99_ms']} ms, "
+            f"same as offline: {same}")
+        lines.append(line)
+        if not same:
+            raise RuntimeError("served results differ from the offline batch")
+    return lines
+
+
+def main(argv=None):
     ap = argparse.ArgumentParser(description="serving benchmark (continuous batching)")
     ap.add_argument("--requests", type=int, default=20000)
     ap.add_argument("--rates", type=float, nargs="+", default=[0.5, 0.8],
@@ -536,54 +596,15 @@ def main(argv=None):
     args = ap.parse_args(argv)
     torch = _torch()
     torch.cuda.set_device(0)
-    batch = seqgen.make_workload("serving", n_pairs=args.requests, seed=args.seed)
     kw = dict(slots=args.slots, long_slots=args.long_slots, max_batch_pairs=args.max_batch_pairs,
               max_batch_bases=args.max_batch_bases, long_batch_pairs=args.long_batch_pairs,
               long_batch_bases=args.long_batch_bases, graphs=not args.no_graphs)
-    res_off, dt_off = offline(batch)
-    cells_pool = count_cells(batch.t_len, batch.q_len, batch.w, res_off)
-    cells = int(cells_pool.sum())
-    sys.stderr.write(f"[serve] offline: {batch.n_pairs} requests as one batch in {dt_off * 1e3:.1f} ms "
-                     f"({batch.n_pairs / dt_off:.0f} req/s, {cells / dt_off / 1e9:.1f} GCUPS)\n")
-    # the server's own capacity: every request waiting at the start
-    run = serve_trace if args.python else serve_trace_native
-    res_sat, lat_sat, wall_sat, nb_sat = run(batch, np.zeros(batch.n_pairs), **kw)
-    capacity = batch.n_pairs / wall_sat
-    sys.stderr.write(f"[serve] saturated: {wall_sat * 1e3:.1f} ms, {capacity:.0f} req/s, {nb_sat} batches, "
-                     f"{cells / wall_sat / 1e9:.1f} GCUPS\n")
-    if not np.array_equal(res_sat, res_off):
-        raise SystemExit("served results differ from the offline batch")
-    long_pool = batch.t_len + batch.q_len > 8000
-    for frac in args.rates:
-        qps = frac * capacity
-        rng = np.random.default_rng([5, args.seed, 1])
-        n_req = batch.n_pairs if args.duration is None else max(1, int(np.ceil(qps * args.duration)))
-        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n_req))
-        pairs = np.arange(n_req) % batch.n_pairs  # request k asks for pool pair k mod pool size
-        res, lat, wall, nb = run(batch, arrivals, pairs=pairs, **kw)
-        same = bool(np.array_equal(res, res_off[pairs]))
-        long_ = long_pool[pairs]
-        req_cells = int(cells_pool[pairs].sum())
-        line = {
-            "metric": "serving latency", "unit": "ms", "qps": round(qps, 1), "rate_of_capacity": frac,
-            "capacity_req_per_s": round(capacity, 1), "requests": n_req, "pool": batch.n_pairs,
-            "served_req_per_s": round(n_req / wall, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-            "p50_short_ms": round(float(np.percentile(lat[~long_], 50)) * 1e3, 3),
-            "p99_short_ms": round(float(np.percentile(lat[~long_], 99)) * 1e3, 3),
-            "p50_long_ms": round(float(np.percentile(lat[long_], 50)) * 1e3, 3) if long_.any() else None,
-            "p99_long_ms": round(float(np.percentile(lat[long_], 99)) * 1e3, 3) if long_.any() else None,
-            "gcups": round(req_cells / wall / 1e9, 3), "offline_gcups": round(cells / dt_off / 1e9, 3),
-            "saturated_gcups": round(cells / wall_sat / 1e9, 3),
-            "batches": nb, "wall_s": round(wall, 3), "same_as_offline": same, "graphs": not args.no_graphs,
-            "host_loop": "python" if args.python else "native",
-            "workload": "seqgen serving workload: 95% pairs of 100-1000 bp (5% errors), 5% of 10-25 kb "
-                        "(1% errors + indels), w=500, Z=400, Poisson arrivals",
-        }
+    try:
+        lines = serving_benchmark(args.requests, args.rates, args.duration, args.seed, args.python, **kw)
+    except RuntimeError as e:
+        raise SystemExit(str(e))
+    for line in lines:
         print(json.dumps(line), flush=True)
-        if not same:
-            raise SystemExit("served results differ from the offline batch")
 
 
 if __name__ == "__main__":
