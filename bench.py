@@ -41,6 +41,8 @@ WORKLOADS = {
                "10% errors 1:1:1, 0.1% N scored -1, a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, seed 0"),
     "longread": ("longread", "HiFi-like long reads: 20k pairs, target U{10000..25000}, 1% errors 1:1:1 plus 1-3 "
                     "indels of U{50..500} bp, a=2 b=4 q=4 e=2 q2=24 e2=1, w=2000, Z=5000, seed 0"),
+    "uniform": ("uniform", "uniform: 500 pairs, target U{100..1000}, 5% errors 2:1:1, a=2 b=4 q=4 e=2 q2=24 "
+                           "e2=1, w=500, Z=400, seed 0"),
     "mixed": ("mix", "heavy-tailed mix: 1M pairs, target min(50000, 50 U^(-1/1.5)), 8% errors 1:1:1, 20% of "
                  "queries with a U{2000..5000} random insert, a=2 b=4 q=4 e=2 q2=24 e2=1, w=751, Z=400, "
                  "seed 0"),
@@ -195,7 +197,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ont",
-                    help="ont (the headline batch, default), longread or mixed")
+                    help="ont (the headline batch, default), longread, mixed or uniform")
     ap.add_argument("--schedule", choices=["persistent", "bucketed"], default="persistent",
                     help="persistent (default) or the plain per-length-bucket launches, for comparison")
     ap.add_argument("--no-autotune", action="store_true",
@@ -208,6 +210,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the persistent-vs-bucketed comparison on the 1M-pair mix")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency runs")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured replays")
     ap.add_argument("--serving-seconds", type=float, default=8.0,
                     help="seconds of Poisson arrivals per serving rate")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -274,6 +277,34 @@ def main():
     step_ms = [a.elapsed_time(b) for a, b in ev]
     log(f"{ms_per_step:.2f} ms per step (device time per step: median {np.median(step_ms):.2f} ms; "
         f"steps {[round(x, 2) for x in step_ms]})")
+
+    # the same call captured into one HIP graph and replayed (outside the
+    # timed steps above; every replay's results are compared with them)
+    graph = None
+    if not args.no_graph:
+        gs = torch.cuda.Stream()
+        gout = torch.empty_like(out)
+        torch.cuda.synchronize()
+        g = ga.AlignGraph(ctx, packed, batch.scoring, batch.w, batch.zdrop, gout, gs)
+        g.launch(gs)
+        gs.synchronize()
+        gms = []
+        for _ in range(args.steps):
+            a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(gs)
+            g.launch(gs)
+            b2.record(gs)
+            gs.synchronize()
+            gms.append(a.elapsed_time(b2))
+        ctx.check()
+        same = bool(torch.equal(gout, out))
+        g.close()
+        if not same:
+            raise RuntimeError("graph replays gave results different from the timed steps")
+        graph = {"steps": args.steps, "ms_median": round(float(np.median(gms)), 3),
+                 "eager_ms_median": round(float(np.median(step_ms)), 3),
+                 "saved_ms": round(float(np.median(step_ms) - np.median(gms)), 3), "same_results": same}
+        log(f"graph replay: median {graph['ms_median']} ms per call (eager {graph['eager_ms_median']} ms)")
 
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
@@ -373,6 +404,7 @@ def main():
             "includes": "host ASCII upload (pageable), packing kernel, alignment, results to host"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "graph": graph,
         "batching": batching,
         "serving": serving,
     }

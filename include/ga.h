@@ -162,6 +162,24 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_
 int ga_align_batch_noalloc(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc,
                            int32_t w, int32_t Z, ga_result_t *out_dev, void *stream);
 
+/* A whole ga_align_batch call captured into a HIP graph (the batched
+ * offline path's launches -- planning, the fork of the context's streams,
+ * every kernel class's persistent launch, the join -- replayed by one
+ * hipGraphLaunch). ga_graph_capture first grows the context's workspace to
+ * the batch and makes its side streams, then captures the call on `stream`
+ * (not NULL) and instantiates the graph; nothing runs on the device. The
+ * graph holds the batch's pointers, sizes, scoring, w and Z and the
+ * context's workspace: ga_graph_launch(graph, stream) then aligns that
+ * batch again (into out_dev) as ga_align_batch would, with the same
+ * results, while the context and every buffer stay alive and no other call
+ * uses the context's workspace in between. Timing must be off and the
+ * schedule persistent or unordered (else GA_EINVAL). */
+typedef struct ga_graph ga_graph_t;
+int ga_graph_capture(ga_context_t *ctx, const ga_batch_t *batch, const ga_scoring_t *sc, int32_t w,
+                     int32_t Z, ga_result_t *out_dev, void *stream, ga_graph_t **graph);
+int ga_graph_launch(ga_graph_t *graph, void *stream);
+int ga_graph_destroy(ga_graph_t *graph);
+
 /* Work schedules of ga_align_batch (results are identical under both):
  * GA_SCHED_PERSISTENT (the default): every pair goes to the cheapest kernel
  * class that runs it, ordered longest first within the class, and each

@@ -35,7 +35,7 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class", "ga_context_set_lanes",
                "ga_host_device_pointer", "ga_server_create", "ga_server_destroy", "ga_server_submit",
                "ga_server_poll", "ga_server_pending", "ga_server_batches", "ga_server_replay",
-               "ga_align_batch_noalloc")
+               "ga_align_batch_noalloc", "ga_graph_capture", "ga_graph_launch", "ga_graph_destroy")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
@@ -129,6 +129,13 @@ def load_library() -> ctypes.CDLL:
     lib.ga_align_batch.restype = ctypes.c_int
     lib.ga_align_batch_noalloc.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), i32, i32, vp, vp]
     lib.ga_align_batch_noalloc.restype = ctypes.c_int
+    lib.ga_graph_capture.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), i32, i32, vp, vp,
+                                     ctypes.POINTER(vp)]
+    lib.ga_graph_capture.restype = ctypes.c_int
+    lib.ga_graph_launch.argtypes = [vp, vp]
+    lib.ga_graph_launch.restype = ctypes.c_int
+    lib.ga_graph_destroy.argtypes = [vp]
+    lib.ga_graph_destroy.restype = ctypes.c_int
     lib.ga_count_cells.argtypes = [i32, i32, i32, i32]
     lib.ga_count_cells.restype = i64
     lib.ga_context_set_timing.argtypes = [vp, ctypes.c_int]
@@ -370,6 +377,35 @@ def ga_align_batch_noalloc(ctx: Context, packed: PackedBatch, scoring: dict, w: 
 
 
 NOALLOC_MAX_PAIRS = 1 << 20
+
+
+class AlignGraph:
+    """One ga_align_batch call captured into a HIP graph (ga_graph_capture):
+    ``launch(stream)`` aligns the same batch into the same output again. The
+    context, the packed batch and ``out`` must outlive it."""
+
+    def __init__(self, ctx: Context, packed: PackedBatch, scoring: dict, w: int, Z: int, out, stream):
+        self._h = ctypes.c_void_p()
+        b = packed.struct()
+        sc = scoring_struct(scoring)
+        self._keep = (ctx, packed, out)
+        _check(load_library().ga_graph_capture(ctx.handle, ctypes.byref(b), ctypes.byref(sc), int(w), int(Z),
+                                               out.data_ptr(), _stream_handle(stream), ctypes.byref(self._h)),
+               "ga_graph_capture")
+
+    def launch(self, stream):
+        _check(load_library().ga_graph_launch(self._h, _stream_handle(stream)), "ga_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().ga_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ga_pair_class(n: int, m: int, w: int) -> int:

@@ -342,36 +342,32 @@ __device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, int f
     update_class<K, KC, C>(st, P, B, ae, be, ee, xe, af, bf, ff, yf);
 }
 
-// The band's right wall is the first diagonal past the band: slot
-// `wall_pos` of the lane flagged in `wall_lanes`. After each update of its
-// class it is forced back to -inf there; its A, E and X are all it feeds
-// forward, so the dead slots beyond it never leave -inf either and nothing
-// crosses the band edge.
-template <int K>
-__device__ __forceinline__ void clamp_wall(PairState<K> &st, uint64_t wall_lanes, int wall_pos) {
-    const bool wl = __builtin_amdgcn_inverse_ballot_w64(wall_lanes);
-    const int wp = __builtin_amdgcn_readfirstlane(wall_pos);
-    if (wl) {  // one lane: indexed register writes under its exec mask
-        st.A[wp] = NEG;
-        st.E[wp] = NEG;
-        st.X[wp] = NEG;
-    }
-}
-
-// A cell that has just left the rectangle (the slot at array position p of
-// the class just updated): it feeds only cells outside the rectangle, so it
-// is forced to -inf with the values its successors read -- A, E, X when it
-// is past the target end (i = n: read from above), A, F, Y when it is past
-// the query end (j = m: read from the left). Its successors then stay -inf,
-// and the lane maxima need no mask for them.
-template <int K, bool PAST_T>
-__device__ __forceinline__ void clamp_cell(PairState<K> &st, int p) {
-    const int pl = __builtin_amdgcn_readfirstlane(p);
-    const bool hit = __builtin_amdgcn_inverse_ballot_w64(1ull << (pl / K));
-    const int sl = pl % K;
-    if (hit) {  // one lane: indexed register writes under its exec mask
+// Force slot `sl` of the one lane in `hit` to -inf in the arrays a clamp
+// kills: A always, E and X (the values read from above) or F and Y (read
+// from the left). The slot always belongs to class C, the class just
+// updated (its diagonal has the parity of the anti-diagonal), so with few
+// slots the write is a select over the class's K/2 slots per array; from
+// 16 slots up an indexed register write (s_set_gpr_idx) is cheaper.
+template <int K, int C, bool EX>
+__device__ __forceinline__ void kill_slot(PairState<K> &st, bool hit, int sl) {
+    if constexpr (K <= 8) {
+        const int t = sl >> 1;  // sl = C + 2t
+#pragma unroll
+        for (int u = 0; u < K / 2; ++u) {
+            if (hit && u == t) {
+                st.A[C + 2 * u] = NEG;
+                if (EX) {
+                    st.E[C + 2 * u] = NEG;
+                    st.X[C + 2 * u] = NEG;
+                } else {
+                    st.F[C + 2 * u] = NEG;
+                    st.Y[C + 2 * u] = NEG;
+                }
+            }
+        }
+    } else if (hit) {  // one lane: indexed register writes under its exec mask
         st.A[sl] = NEG;
-        if (PAST_T) {
+        if (EX) {
             st.E[sl] = NEG;
             st.X[sl] = NEG;
         } else {
@@ -379,6 +375,30 @@ __device__ __forceinline__ void clamp_cell(PairState<K> &st, int p) {
             st.Y[sl] = NEG;
         }
     }
+}
+
+// The band's right wall is the first diagonal past the band: slot
+// `wall_pos` of the lane flagged in `wall_lanes` (a slot of class C). After
+// each update of its class it is forced back to -inf there; its A, E and X
+// are all it feeds forward, so the dead slots beyond it never leave -inf
+// either and nothing crosses the band edge.
+template <int K, int C>
+__device__ __forceinline__ void clamp_wall(PairState<K> &st, uint64_t wall_lanes, int wall_pos) {
+    const bool wl = __builtin_amdgcn_inverse_ballot_w64(wall_lanes);
+    kill_slot<K, C, true>(st, wl, __builtin_amdgcn_readfirstlane(wall_pos));
+}
+
+// A cell that has just left the rectangle (the slot at array position p of
+// class C, just updated): it feeds only cells outside the rectangle, so it
+// is forced to -inf with the values its successors read -- A, E, X when it
+// is past the target end (i = n: read from above), A, F, Y when it is past
+// the query end (j = m: read from the left). Its successors then stay -inf,
+// and the lane maxima need no mask for them.
+template <int K, int C, bool PAST_T>
+__device__ __forceinline__ void clamp_cell(PairState<K> &st, int p) {
+    const int pl = __builtin_amdgcn_readfirstlane(p);
+    const bool hit = __builtin_amdgcn_inverse_ballot_w64(1ull << (pl / K));
+    kill_slot<K, C, PAST_T>(st, hit, pl % K);
 }
 
 // Geometry of one pair (all wave-uniform).
@@ -424,11 +444,23 @@ struct Ring {
     static_assert(WORDS >= 8 * K + 4 + WAVE, "a block's windows and one refill must fit the ring");
 };
 
+// One sequence's bases in HBM: its first 2-bit word, the stream's N bitmap
+// (or null) and the bit of its first base there, its length.
+struct SeqSource {
+    const uint32_t *words;
+    const uint32_t *nmask;
+    int64_t nbit0;
+    int64_t len;
+};
+
 template <int K, int NW>
 struct PairLds {
     int park[K * WAVE];  // park[s * 64 + lane] = A of slot s
-    // each wave's staged bases: [wave][0 target, 1 query]
+    // each wave's staged bases: [wave][0 target, 1 query], and where they
+    // come from (read only when a ring is refilled, so the sweep keeps no
+    // registers for them)
     uint32_t ring[NW][2][Ring<K>::WORDS + Ring<K>::MIRROR];
+    SeqSource src[NW][2];
     // several waves (double-buffered by exchange): the owned edge diagonals
     // a wave hands its neighbours (A, E, X, F, Y of two slots each way) and
     // the wave maxima of the exchange's two anti-diagonals
@@ -785,7 +817,10 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
     const int t1 = 1 - r0;  // first step with an anti-diagonal to finish
     const int pi0 = 2 * g.n - r0 + 1 - g.a0w;
     const int pj0 = r0 - 1 - 2 * g.m - g.a0w;
-    const uint32_t bits_i = step_bits(max(max(t1, 2 * g.n - r0 + 1 - g.a1), pi0 - WAVE * K + 1), pi0);
+    // the cell (n, -1) is clamped too when the band reaches the target's end
+    // (a1 = n: no wall then, see align_pair)
+    const int a1x = g.a1 + (g.a1 == g.n ? 1 : 0);
+    const uint32_t bits_i = step_bits(max(max(t1, 2 * g.n - r0 + 1 - a1x), pi0 - WAVE * K + 1), pi0);
     const uint32_t bits_j = step_bits(max(max(t1, g.a0 + 2 * g.m + 1 - r0), -pj0), WAVE * K - 1 - pj0);
     const uint32_t bits_w = wall_lanes != 0 ? ((wall_pos & 1) ? 0x55u : 0xAAu) & step_bits(t1, 7) : 0u;
     const uint32_t bits_ring = step_bits(t1, max(g.a1, -g.a0) - r0 - 1);
@@ -797,9 +832,9 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
         const int r = r0 + (T);                                                            \
         if (r >= 0) {                                                                      \
             const int rp = r - 1;                                                          \
-            if (bits_w & (1u << (T))) clamp_wall<K>(st, wall_lanes, wall_pos);             \
-            if (bits_i & (1u << (T))) clamp_cell<K, true>(st, pi0 - (T));                  \
-            if (bits_j & (1u << (T))) clamp_cell<K, false>(st, pj0 + (T));                 \
+            if (bits_w & (1u << (T))) clamp_wall<K, CP>(st, wall_lanes, wall_pos);         \
+            if (bits_i & (1u << (T))) clamp_cell<K, CP, true>(st, pi0 - (T));              \
+            if (bits_j & (1u << (T))) clamp_cell<K, CP, false>(st, pj0 + (T));             \
             int lm = lane_max<K, CP, 1>(st, g, 0, 0, false);                               \
             int MA = wave_max(lm);                                                         \
             dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                       \
@@ -862,7 +897,8 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
     const int t0 = -r0;
     const int pi0 = 2 * g.n - r0 - g.a0w;
     const int pj0 = r0 - 2 * g.m - g.a0w;
-    const uint32_t bits_i = step_bits(max(max(t0, 2 * g.n - r0 - g.a1), pi0 - WAVE * K + 1), pi0);
+    const int a1x = g.a1 + (g.a1 == g.n ? 1 : 0);  // (n, -1) too when a1 = n (no wall)
+    const uint32_t bits_i = step_bits(max(max(t0, 2 * g.n - r0 - a1x), pi0 - WAVE * K + 1), pi0);
     const uint32_t bits_j = step_bits(max(max(t0, g.a0 + 2 * g.m - r0), -pj0), WAVE * K - 1 - pj0);
     const uint32_t bits_w = wall_lanes != 0 ? ((wall_pos & 1) ? 0xAAu : 0x55u) & step_bits(t0, 7) : 0u;
     const uint32_t bits_ring = step_bits(t0, max(g.a1, -g.a0) - r0 - 2);
@@ -872,9 +908,9 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
         constexpr int KC = (T) >> 1;                                                  \
         if (r0 + (T) >= 0) {                                                          \
             dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                  \
-            if (bits_w & (1u << (T))) clamp_wall<K>(st, wall_lanes, wall_pos);        \
-            if (bits_i & (1u << (T))) clamp_cell<K, true>(st, pi0 - (T));             \
-            if (bits_j & (1u << (T))) clamp_cell<K, false>(st, pj0 + (T));            \
+            if (bits_w & (1u << (T))) clamp_wall<K, C>(st, wall_lanes, wall_pos);     \
+            if (bits_i & (1u << (T))) clamp_cell<K, C, true>(st, pi0 - (T));          \
+            if (bits_j & (1u << (T))) clamp_cell<K, C, false>(st, pj0 + (T));         \
             LM = lane_max<K, C, NW>(st, g, 0, 0, false);                              \
             MAW = wave_max(LM);                                                       \
         }                                                                             \
@@ -948,25 +984,28 @@ __device__ __forceinline__ uint32_t expand4(uint32_t c8, uint32_t n4) {
     return codes | (((n4 * 0x00204081u) & 0x01010101u) << 2);
 }
 
-// Make the ring of one sequence (2-bit words from word `off` of `words`,
-// N bitmap `nmask` of the whole stream or null, `len` bases) hold the ring
-// words [wlo, whi) (word x = positions 4x .. 4x+3). The ring holds the words
-// below `filled` (wave-uniform); when the block needs more, lanes fill the
-// next 64 words at once, one each (bases past the sequence are left as they
-// are), until it holds enough. Rare: once every 64 words of advance.
+// Make the ring of one sequence hold the ring words [wlo, whi) (word x =
+// positions 4x .. 4x+3). The ring holds the words below `filled`
+// (wave-uniform); when the block needs more, lanes fill the next 64 words
+// at once, one each (bases past the sequence are left as they are), until
+// it holds enough. Rare: once every 64 words of advance. The source comes
+// from LDS, where the wave put it when the pair started.
 template <int K>
-__device__ __forceinline__ void refill(uint32_t *ring, const uint32_t *words, const uint32_t *nmask, int64_t off,
-                                       int len, int &filled, int wlo, int whi, int lane) {
+__device__ __forceinline__ void refill(uint32_t *ring, const SeqSource *src, int &filled, int wlo, int whi,
+                                    int lane) {
     constexpr int WORDS = Ring<K>::WORDS, MIRROR = Ring<K>::MIRROR;
+    const uint32_t *words = src->words;
+    const uint32_t *nmask = src->nmask;
+    const int64_t nbit0 = src->nbit0;
+    const int wend = (int)((src->len + 3) >> 2);
     if (filled < wlo) filled = wlo;  // nothing below the windows is needed
-    const int wend = (len + 3) >> 2;
     do {
         const int x = filled + lane;
         if (x < wend) {
-            const uint32_t w = words[off + (x >> 2)];
+            const uint32_t w = words[x >> 2];
             uint32_t n4 = 0;
             if (nmask) {
-                const int64_t bit = 16 * off + 4 * (int64_t)x;
+                const int64_t bit = nbit0 + 4 * (int64_t)x;
                 n4 = (nmask[bit >> 5] >> (int)(bit & 31)) & 0xFu;
             }
             const uint32_t v = expand4((w >> (8 * (x & 3))) & 0xFFu, n4);
@@ -983,18 +1022,16 @@ __device__ __forceinline__ void refill(uint32_t *ring, const uint32_t *words, co
 // [I0, I0 + 32K + 4) and query positions [J0 - 32K + 1, J0 + 4) of lane
 // 0's I0, J0, clipped to the sequences. `ft`, `fq`: the rings' watermarks.
 template <int K>
-__device__ __forceinline__ void stage_block(const DpArgs &P, int p, const Geo &g, uint32_t *ring_t,
-                                            uint32_t *ring_q, int &ft, int &fq, int r, int b, int lane) {
+__device__ __forceinline__ void stage_block(const Geo &g, uint32_t *ring_t, uint32_t *ring_q,
+                                            const SeqSource *src, int &ft, int &fq, int r, int b, int lane) {
     const int I0 = (r + b) >> 1, J0 = (r - b) >> 1;
     {
         const int lo = max(I0, 0), hi = min(I0 + 32 * K + 4, g.n);
-        if (lo < hi && ((hi + 3) >> 2) > ft)
-            refill<K>(ring_t, P.tw, P.tn, P.t_off[p], g.n, ft, lo >> 2, (hi + 3) >> 2, lane);
+        if (lo < hi && ((hi + 3) >> 2) > ft) refill<K>(ring_t, src, ft, lo >> 2, (hi + 3) >> 2, lane);
     }
     {
         const int lo = max(J0 - 32 * K + 1, 0), hi = min(J0 + 4, g.m);
-        if (lo < hi && ((hi + 3) >> 2) > fq)
-            refill<K>(ring_q, P.qw, P.qn, P.q_off[p], g.m, fq, lo >> 2, (hi + 3) >> 2, lane);
+        if (lo < hi && ((hi + 3) >> 2) > fq) refill<K>(ring_q, src + 1, fq, lo >> 2, (hi + 3) >> 2, lane);
     }
     __builtin_amdgcn_wave_barrier();  // the ring writes precede the window reads
 }
@@ -1108,12 +1145,15 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     const int slide = (SL && D > WAVE * K) ? (n <= m ? -1 : 1) : 0;
     int r0 = (g.a0 & 1) ? -1 : -2;  // blocks of 8 anti-diagonals start on the class of slot 0
     if (slide < 0) g.a0w = g.a0 + K * max(0, (-r0 - 9 - g.a0) / K);
-    // the right wall: the slot of diagonal a1+1, if this wave holds it
+    // the right wall: the slot of diagonal a1+1, if this wave holds it.
+    // When the band reaches the target's end (a1 = n) every cell on that
+    // diagonal lies past the target's end: the exit-cell clamp of (n, -1)
+    // keeps it at -inf instead, with no clamp on the other steps.
     int wall_pos = 0;
     uint64_t wall_lanes = 0;
     auto place_wall = [&]() {
         const int Dw = a1 + 1 - g.a0w;
-        const bool has_wall = Dw >= 0 && Dw < WAVE * K;
+        const bool has_wall = Dw >= 0 && Dw < WAVE * K && a1 < n;
         wall_pos = has_wall ? Dw % K : 0;
         wall_lanes = has_wall ? (1ull << (Dw / K)) : 0ull;
     };
@@ -1151,10 +1191,16 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     }
     Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false};
 
-    // this wave's base rings, filled for the first block
+    // this wave's base rings and their sources, filled for the first block
     uint32_t *ring_t = S.ring[wv][0], *ring_q = S.ring[wv][1];
+    if (lane == 0) {
+        const int64_t to = P.t_off[p], qo = P.q_off[p];
+        S.src[wv][0] = SeqSource{P.tw + to, P.tn, 16 * to, n};
+        S.src[wv][1] = SeqSource{P.qw + qo, P.qn, 16 * qo, m};
+    }
+    __builtin_amdgcn_wave_barrier();
     int ft = -(1 << 30), fq = -(1 << 30);
-    stage_block<K>(P, p, g, ring_t, ring_q, ft, fq, r0, g.a0w, lane);
+    stage_block<K>(g, ring_t, ring_q, S.src[wv], ft, fq, r0, g.a0w, lane);
     Windows<K> wd;
     load_windows<K>(wd, ring_t, ring_q, r0, d0);
     int base_next = g.a0w;
@@ -1169,7 +1215,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         }
         build_scores<K>(st, wd, P);
         base_next = slide != 0 ? window_base<K>(g, slide, g.a0w, r0 + 8) : g.a0w;
-        stage_block<K>(P, p, g, ring_t, ring_q, ft, fq, r0 + 8, base_next, lane);
+        stage_block<K>(g, ring_t, ring_q, S.src[wv], ft, fq, r0 + 8, base_next, lane);
         load_windows<K>(wd, ring_t, ring_q, r0 + 8, base_next + lane * K);  // next block, in flight
         bool done;
         if constexpr (NW == 1)
@@ -2257,6 +2303,63 @@ int ga_align_batch(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *
     if (rc == GA_OK && ctx->lanes > 1 && ctx->schedule != GA_SCHED_BUCKETED) rc = make_side_streams(ctx);
     if (rc != GA_OK) return rc;
     return align_launch(ctx, bt, sc, w, Z, out_dev, (hipStream_t)stream, (char *)ctx->ws);
+}
+
+struct ga_graph {
+    int device;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int ga_graph_capture(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w, int32_t Z,
+                     ga_result_t *out_dev, void *stream, ga_graph_t **graph) {
+    if (!graph) return GA_EINVAL;
+    *graph = nullptr;
+    int rc = validate_call(ctx, bt, sc, w, Z, out_dev);
+    if (rc != GA_OK) return rc;
+    if (!stream || bt->n_pairs == 0 || ctx->timing || ctx->schedule == GA_SCHED_BUCKETED) return GA_EINVAL;
+    SetDevice sd(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    // everything the call needs exists before capture: the workspace at this
+    // batch's size and the side streams
+    rc = ensure_ws(ctx, ws_bytes((size_t)bt->n_pairs));
+    if (rc == GA_OK && ctx->lanes > 1) rc = make_side_streams(ctx);
+    if (rc != GA_OK) return rc;
+    ga_graph *g = (ga_graph *)calloc(1, sizeof(ga_graph));
+    if (!g) return GA_ENOMEM;
+    g->device = ctx->device;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        free(g);
+        return GA_EHIP;
+    }
+    rc = align_launch(ctx, bt, sc, w, Z, out_dev, s, (char *)ctx->ws);
+    const bool ended = hipStreamEndCapture(s, &g->graph) == hipSuccess;
+    if (rc == GA_OK && (!ended || !g->graph)) rc = GA_EHIP;
+    if (rc == GA_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) rc = GA_EHIP;
+    if (rc != GA_OK) {
+        (void)hipGetLastError();
+        if (g->graph) hipGraphDestroy(g->graph);
+        free(g);
+        return rc;
+    }
+    *graph = g;
+    return GA_OK;
+}
+
+int ga_graph_launch(ga_graph_t *g, void *stream) {
+    if (!g || !g->exec) return GA_EINVAL;
+    SetDevice sd(g->device);
+    return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? GA_OK : GA_EHIP;
+}
+
+int ga_graph_destroy(ga_graph_t *g) {
+    if (!g) return GA_EINVAL;
+    SetDevice sd(g->device);
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    free(g);
+    return GA_OK;
 }
 
 int ga_align_batch_noalloc(ga_context_t *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, int32_t w,

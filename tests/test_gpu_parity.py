@@ -3,6 +3,7 @@ same seeded inputs, bit-exact on all seven int32 result fields."""
 
 from __future__ import annotations
 
+import ctypes
 import os
 import sys
 
@@ -703,6 +704,48 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
     for slot in slots.values():
         slot.ctx.close()
+
+
+def test_offline_graph_replays():
+    """One whole ga_align_batch call (planning, the fork over the context's
+    four streams, every class launch, the join) captured into a HIP graph:
+    each of several replays -- with unrelated eager work and a full
+    synchronisation between them -- equals the eager call, which matches
+    the oracle. The captured call's output is cleared before every replay."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    full = seqgen.make_workload("mix", n_pairs=3000, seed=7)
+    b = full.subset(np.nonzero(full.t_len <= 6000)[0][:1500])
+    ctx = ga.Context(0)
+    packed = ga.pack_batch(ctx, b)
+    eager = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+    torch.cuda.synchronize()
+    ctx.check()
+    eager = eager.cpu().numpy()
+    want, _ = oracle_align(b)
+    assert_same(eager, want, b, "graph eager")
+    s = torch.cuda.Stream()  # default priority; capture needs a stream of its own
+    out = torch.full((b.n_pairs, 7), -9, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    lib = ga.load_library()
+    bad = ctypes.c_void_p()
+    assert lib.ga_graph_capture(ctx.handle, ctypes.byref(packed.struct()), ctypes.byref(ga.scoring_struct(b.scoring)),
+                                b.w, b.zdrop, out.data_ptr(), None, ctypes.byref(bad)) == ga.GA_EINVAL
+    g = ga.AlignGraph(ctx, packed, b.scoring, b.w, b.zdrop, out, s)
+    for k in range(3):
+        out.fill_(-9)
+        torch.cuda.synchronize()
+        _say(f"offline graph replay {k}: {b.n_pairs} pairs")
+        g.launch(s)
+        s.synchronize()
+        ctx.check()
+        assert np.array_equal(out.cpu().numpy(), eager), k
+        x = torch.arange(1 << 20, device="cuda", dtype=torch.int32)
+        assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
+        torch.cuda.synchronize()
+    g.close()
+    ctx.close()
 
 
 def test_autotune_order_and_results():
