@@ -200,6 +200,8 @@ def main():
                     help="ont (the headline batch, default), longread, mixed or uniform")
     ap.add_argument("--schedule", choices=["persistent", "bucketed"], default="persistent",
                     help="persistent (default) or the plain per-length-bucket launches, for comparison")
+    ap.add_argument("--lanes", type=int, default=None,
+                    help="streams the class launches spread over (1..4; default: the library's)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default class order instead of the measured one")
     ap.add_argument("--pairs", type=int, default=None, help="fewer pairs (profiling runs only)")
@@ -237,6 +239,8 @@ def main():
     batch = seqgen.make_workload(wid, n_pairs=args.pairs)
     ctx = ga.Context(0)
     ctx.set_schedule(args.schedule)
+    if args.lanes is not None:
+        ctx.set_lanes(args.lanes)
     class_cost = None
     if not args.no_autotune:
         # set-up, outside the timed steps: measure each kernel class, then

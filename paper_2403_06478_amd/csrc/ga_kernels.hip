@@ -220,6 +220,9 @@ struct DpArgs {
     int32_t w, Z;
     int32_t q1, c2, d2, e1, e2;
     int32_t oe1, oe2;
+    // frame value of the boundary cells (-1, r+1), (r+1, -1) of
+    // anti-diagonal r (H = -gamma(r+2)): max(ring_a0, ring_b0 + r * ring_d)
+    int32_t ring_a0, ring_b0, ring_d;
     uint32_t lut_lo, lut_hi;  // s' per class byte (signed bytes)
 };
 
@@ -421,6 +424,11 @@ struct Track {
     int g_r, g_base, g_cls, g_ma;  // g_base: diagonal of lane 0's slot 0 in the holding wave
     bool g_open;  // G moved since its cell was last resolved
     bool g_set;   // G has moved off the origin
+    // one wave per pair: G in the score frame of the anti-diagonal being
+    // decided (advanced by e per anti-diagonal), so the decisions compare
+    // frame values and never convert back to scores; G itself is
+    // g_ma + q - e * g_r
+    int gf;
 };
 
 // LDS of one pair's workgroup: the park of the wave holding the global
@@ -599,9 +607,9 @@ __device__ __forceinline__ int lane_max(const PairState<K> &st, const Geo &g, in
 // ends at its last anti-diagonal and 2 on a z-drop.
 template <int K, int C>
 __device__ __forceinline__ void take_max(const PairState<K> &st, const Geo &g, Track &tr, int r, int lane,
-                                         int MA, int M, PairLds<K, 1> &S) {
+                                         int MA, PairLds<K, 1> &S) {
     park_class<K, C, 1>(st, S, lane);
-    tr.G = M;
+    tr.gf = MA;
     tr.g_r = r;
     tr.g_base = g.a0w;
     tr.g_cls = C;
@@ -612,16 +620,18 @@ __device__ __forceinline__ void take_max(const PairState<K> &st, const Geo &g, T
 
 template <int K, int C>
 __device__ __forceinline__ int finish_diag(const PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
-                                           int r, int lane, int lm, int MA, int M, bool up, int vlo, int vhi,
+                                           int r, int lane, int lm, int MA, bool up, int vlo, int vhi,
                                            bool masked, PairLds<K, 1> &S) {
     const bool last = r >= g.r_last;
     if (!masked) diag_window(g, r, vlo, vhi);
     int mi, mj;
     locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
-    tr.endS = M;
+    tr.endS = MA + P.q1 - P.e1 * r;  // back to the true score
     tr.endI = mi;
     tr.endJ = mj;
-    if (!up && P.Z >= 0 && tr.G - M > P.Z) {
+    // G - M, in the frame of anti-diagonal r
+    const int drop = tr.gf - MA;
+    if (!up && P.Z >= 0 && drop > P.Z) {
         if (tr.g_open) {
             int gi, gj;
             park_cell<K, 1>(tr, g, S, lane, gi, gj);
@@ -632,7 +642,7 @@ __device__ __forceinline__ int finish_diag(const PairState<K> &st, const DpArgs 
         if (mi > tr.gi && mj > tr.gj) {
             int dd = (mi - tr.gi) - (mj - tr.gj);
             dd = dd < 0 ? -dd : dd;
-            if (tr.G - M > P.Z + P.e2 * dd) return 2;
+            if (drop > P.Z + P.e2 * dd) return 2;
         }
     }
     return last ? 1 : 0;
@@ -824,6 +834,7 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
     const uint32_t bits_j = step_bits(max(max(t1, g.a0 + 2 * g.m + 1 - r0), -pj0), WAVE * K - 1 - pj0);
     const uint32_t bits_w = wall_lanes != 0 ? ((wall_pos & 1) ? 0x55u : 0xAAu) & step_bits(t1, 7) : 0u;
     const uint32_t bits_ring = step_bits(t1, max(g.a1, -g.a0) - r0 - 1);
+    const int ring_r0 = P.ring_b0 + P.ring_d * r0;  // boundary value's linear piece at r0
 #define GA_STEP1(T)                                                                        \
     {                                                                                      \
         constexpr int C = (T) & 1;                                                         \
@@ -841,20 +852,21 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
             if (r >= 1) {                                                                  \
                 int vlo = 0, vhi = 0;                                                      \
                 bool mp = false;                                                           \
-                if (__builtin_expect((bits_ring & (1u << (T))) && MA == ring_a(P, rp), 0)) { \
+                if (__builtin_expect((bits_ring & (1u << (T))) &&                          \
+                                     MA == max(P.ring_a0, ring_r0 + P.ring_d * ((T) - 1)), 0)) { \
                     /* a boundary cell may hold the maximum: redo it masked */             \
                     mp = true;                                                             \
                     diag_window(g, rp, vlo, vhi);                                          \
                     lm = lane_max<K, CP, 1>(st, g, vlo, vhi, true);                        \
                     MA = wave_max(lm);                                                     \
                 }                                                                          \
+                tr.gf += P.e1;  /* G's frame value on anti-diagonal rp */                 \
                 if (MA > LIVE_MIN) {  /* the anti-diagonal has an interior cell */         \
-                    const int M = MA + P.q1 - P.e1 * rp;  /* back to the true score */     \
-                    const bool up = M > tr.G;                                              \
-                    if (up) take_max<K, CP>(st, g, tr, rp, lane, MA, M, S);                \
+                    const bool up = MA > tr.gf;                                            \
+                    if (up) take_max<K, CP>(st, g, tr, rp, lane, MA, S);                   \
                     if (__builtin_expect(rp >= g.r_last ||                                 \
-                                         (!up && P.Z >= 0 && tr.G - M > P.Z), 0)) {       \
-                        const int rc = finish_diag<K, CP>(st, P, g, tr, rp, lane, lm, MA, M, up, \
+                                         (!up && P.Z >= 0 && tr.gf - MA > P.Z), 0)) {     \
+                        const int rc = finish_diag<K, CP>(st, P, g, tr, rp, lane, lm, MA, up, \
                                                           vlo, vhi, mp, S);                \
                         if (rc) {                                                          \
                             tr.zd = rc >> 1;                                               \
@@ -1189,7 +1201,9 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
             }
         }
     }
-    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false};
+    // G = 0 at the origin, in the frame of anti-diagonal -1 (the first
+    // decision, for anti-diagonal 0, advances it)
+    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false, -P.q1 - P.e1};
 
     // this wave's base rings and their sources, filled for the first block
     uint32_t *ring_t = S.ring[wv][0], *ring_q = S.ring[wv][1];
@@ -1233,7 +1247,8 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
             tr.gj = gj;
         }
         if (lane < 7) {
-            const int v[7] = {tr.G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
+            const int G = tr.g_set ? tr.g_ma + P.q1 - P.e1 * tr.g_r : 0;
+            const int v[7] = {G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
             int val = v[0];
 #pragma unroll
             for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
@@ -2215,6 +2230,10 @@ int align_launch(ga_context *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, 
     da.e2 = sc->e2;
     da.oe1 = sc->q + sc->e;
     da.oe2 = sc->q2 + sc->e2;
+    // -gamma(r+2) - q + e*r = max(-2q - 2e, -(q2 + e2) - e2 - q + r*(e - e2))
+    da.ring_a0 = -2 * sc->q - 2 * sc->e;
+    da.ring_b0 = -(sc->q2 + sc->e2) - sc->e2 - sc->q;
+    da.ring_d = sc->e - sc->e2;
     {
         const int fold = sc->q + 2 * sc->e;  // frame drift over the diagonal step
         const uint32_t A = (uint32_t)(uint8_t)(int8_t)(sc->a + fold);
