@@ -178,17 +178,27 @@ def serving_summary(duration_s: float):
     """Serving at 0.5 and 0.8 of the server's saturated throughput (the
     serving workload, native host loop, captured graphs): p50/p99 per rate
     for short and long requests, every result checked against the offline
-    batch."""
-    from paper_2403_06478_amd import serve
+    batch. Runs as a child process with a HIP runtime of its own: the
+    streams this process already made would share the GPU's few hardware
+    queues with the server's slot streams and serialise its batches."""
+    import subprocess
 
-    lines = serve.serving_benchmark(requests=20000, rates=(0.5, 0.8), duration=duration_s, log=log)
+    cmd = [sys.executable, "-u", "-m", "paper_2403_06478_amd.serve", "--requests", "20000",
+           "--rates", "0.5", "0.8", "--duration", str(duration_s)]
+    log(f"serving: {' '.join(cmd[2:])}")
+    res = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True)
+    for line in res.stderr.splitlines():
+        if line.startswith("[serve]"):
+            log(line)
+    if res.returncode != 0:
+        raise RuntimeError(f"serving benchmark failed ({res.returncode}): {res.stderr[-2000:]}")
+    lines = [json.loads(l) for l in res.stdout.splitlines() if l.startswith("{")]
     keep = ("rate_of_capacity", "qps", "requests", "served_req_per_s", "p50_ms", "p99_ms", "p50_short_ms",
             "p99_short_ms", "p50_long_ms", "p99_long_ms", "gcups", "same_as_offline")
-    out = {"workload": lines[0]["workload"], "capacity_req_per_s": lines[0]["capacity_req_per_s"],
-           "offline_gcups": lines[0]["offline_gcups"], "saturated_gcups": lines[0]["saturated_gcups"],
-           "duration_s_per_rate": duration_s, "host_loop": lines[0]["host_loop"], "graphs": lines[0]["graphs"],
-           "latency": "arrival to results visible on the host", "rates": [{k: l[k] for k in keep} for l in lines]}
-    return out
+    return {"workload": lines[0]["workload"], "capacity_req_per_s": lines[0]["capacity_req_per_s"],
+            "offline_gcups": lines[0]["offline_gcups"], "saturated_gcups": lines[0]["saturated_gcups"],
+            "duration_s_per_rate": duration_s, "host_loop": lines[0]["host_loop"], "graphs": lines[0]["graphs"],
+            "latency": "arrival to results visible on the host", "rates": [{k: l[k] for k in keep} for l in lines]}
 
 
 def main():

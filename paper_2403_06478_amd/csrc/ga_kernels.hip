@@ -400,8 +400,17 @@ __device__ __forceinline__ void clamp_wall(PairState<K> &st, uint64_t wall_lanes
 template <int K, int C, bool PAST_T>
 __device__ __forceinline__ void clamp_cell(PairState<K> &st, int p) {
     const int pl = __builtin_amdgcn_readfirstlane(p);
-    const bool hit = __builtin_amdgcn_inverse_ballot_w64(1ull << (pl / K));
-    kill_slot<K, C, PAST_T>(st, hit, pl % K);
+    if constexpr (K == 4 || K == 8) {
+        // 0 <= p < 64K: shift and mask (with K >= 16 the slot index feeds
+        // an indexed register write, which the signed form keeps in
+        // registers)
+        const unsigned pu = (unsigned)pl;
+        const bool hit = __builtin_amdgcn_inverse_ballot_w64(1ull << (pu / K));
+        kill_slot<K, C, PAST_T>(st, hit, (int)(pu % K));
+    } else {
+        const bool hit = __builtin_amdgcn_inverse_ballot_w64(1ull << (pl / K));
+        kill_slot<K, C, PAST_T>(st, hit, pl % K);
+    }
 }
 
 // Geometry of one pair (all wave-uniform).
@@ -1102,12 +1111,18 @@ __device__ __forceinline__ int window_base(const Geo &g, int slide, int base, in
 // slots, then every lane reads the row of its neighbour; rows 0 and 65 hold
 // -inf for the lane with no neighbour on that side. Staging costs no
 // registers beyond the state, and the rows are reused array after array.
+// A sliding window's workgroup is one wave, whose LDS operations complete
+// in order: a wave-level scheduling barrier keeps the compiler from moving
+// the reads above the writes (or the next array's writes above the reads),
+// and no workgroup barrier is needed.
 template <int K>
 __device__ __forceinline__ void shift_array(typename PairState<K>::VecK &a, int *rows, int lane, int dir) {
     int4 *own = reinterpret_cast<int4 *>(rows + (lane + 1) * K);
 #pragma unroll
     for (int q = 0; q < K / 4; ++q) own[q] = make_int4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
-    __syncthreads();  // every row is staged before any lane reads its neighbour's
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // every row is staged before any lane reads its neighbour's
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int4 *from = reinterpret_cast<const int4 *>(rows + (lane + 1 + dir) * K);
 #pragma unroll
     for (int q = 0; q < K / 4; ++q) {
@@ -1117,7 +1132,9 @@ __device__ __forceinline__ void shift_array(typename PairState<K>::VecK &a, int 
         a[4 * q + 2] = v.z;
         a[4 * q + 3] = v.w;
     }
-    __syncthreads();  // every lane has read before the next array is staged
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // every lane has read before the next array is staged
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int K>
