@@ -350,7 +350,7 @@ def main():
     t_len, q_len = batch.t_len, batch.q_len
     cells = ga.count_cells(t_len, q_len, batch.w, res)
     # the class each pair ran in (this context's autotuned order)
-    cls = np.array([ctx.pair_class(int(n), int(m), batch.w) for n, m in zip(t_len, q_len)])
+    cls = np.array([ctx.pair_class(int(n), int(m), batch.w, batch.n_pairs) for n, m in zip(t_len, q_len)])
     total_cells = int(cells.sum())
     gcups = total_cells / (ms_per_step / 1e3) / 1e9
     e2e_ms_med = float(np.median(e2e_ms)) if e2e_ms else None

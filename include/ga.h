@@ -213,7 +213,7 @@ int ga_context_set_lanes(ga_context_t *ctx, int lanes);
 
 /* Restrict the kernel classes (bit c = class c, see ga_context_timing) that
  * later ga_align_batch calls on this context may use; the default is all
- * twelve. Each pair takes the cheapest allowed class that runs it in the
+ * fifteen. Each pair takes the cheapest allowed class that runs it in the
  * shape the cheapest-first rule gives that class (a sliding class only for a
  * band wider than its window, a class of W waves only for a band that
  * reaches its last wave: more than 64*K*(W-1) diagonals). A pair that no
@@ -221,7 +221,7 @@ int ga_context_set_lanes(ga_context_t *ctx, int lanes);
  * GA_EDEVICE (see ga_context_check). For sensitivity studies of the kernel
  * shapes (the slice width of Section 5.5 and the subwarp size of Section 5.7 have
  * their counterparts in the slots per lane and the waves per pair). Returns
- * GA_EINVAL for an empty mask or bits above class 11. */
+ * GA_EINVAL for an empty mask or bits above class 14. */
 int ga_context_set_classes(ga_context_t *ctx, uint32_t mask);
 
 /* Autotuner (the context's autotune table): runs a synthetic probe batch
@@ -229,15 +229,37 @@ int ga_context_set_classes(ga_context_t *ctx, uint32_t mask);
  * about one substitution in 16, in the shape the cheapest-first rule gives
  * each class (the band filling 7/8 of its slots; short-by-long pairs for the
  * sliding classes), enough pairs for two rounds of resident workgroups --
- * and times each class's launch. ns_per_step[c] (c < n, n <= 12) receives
+ * and times each class's launch. ns_per_step[c] (c < n, n <= 15) receives
  * the measured cost of class c in nanoseconds per pair and anti-diagonal at
  * full occupancy. Later ga_align_batch calls on this context then try the
  * classes cheapest first: each pair takes the cheapest allowed class that
  * runs it (results do not depend on the class). This is where the shape
  * choices of Sections 5.5 and 5.7 (slice width, subwarp size) are made by
- * measurement. Allocates temporary device memory and synchronises
- * `stream`; on an error the default order is in force. */
+ * measurement. It also times each class on a batch of 64 such pairs, each
+ * alone on its CU: one pair's time per anti-diagonal (its latency, see
+ * ga_context_class_latency). Calls of at most 2 x (compute units) pairs
+ * then use the classes in that order instead: such a batch does not fill
+ * the GPU and takes as long as its longest sweep, so a band spread over
+ * more waves (shorter steps, classes 12-14) can end it sooner even though
+ * it costs more per pair at full occupancy. Allocates temporary device
+ * memory and synchronises `stream`; on an error the default order is in
+ * force (and no latency order). */
 int ga_context_autotune(ga_context_t *ctx, float *ns_per_step, int n, void *stream);
+
+/* The latency the autotuner measured per class (ns per anti-diagonal of one
+ * pair in a batch of 64), into ns_per_step[c] for c < n; GA_EINVAL if the
+ * context was not autotuned. */
+int ga_context_class_latency(const ga_context_t *ctx, float *ns_per_step, int n);
+
+/* Calls of at most n_pairs pairs plan with the latency order (0: never);
+ * the autotuner sets 2 x (compute units). GA_EINVAL if the context was not
+ * autotuned or n_pairs < 0. */
+int ga_context_set_latency_pairs(ga_context_t *ctx, int32_t n_pairs);
+
+/* The class a call of n_pairs pairs on this context picks for a pair of
+ * lengths n, m at band w (the latency or throughput order, see
+ * ga_context_autotune); -1 if none. */
+int ga_context_batch_class(const ga_context_t *ctx, int32_t n, int32_t m, int32_t w, int64_t n_pairs);
 
 /* The class ga_align_batch on this context picks for a pair of lengths
  * n, m at band w (its class mask and autotuned order); -1 if none. */
@@ -250,18 +272,19 @@ int ga_context_set_timing(ga_context_t *ctx, int enable);
 /* Milliseconds spent by the stages of the last timed ga_align_batch on this
  * context (waits for those events): ms[0] = planning kernels,
  * ms[1+c] = the alignment launches of class c (summed over buckets under
- * GA_SCHED_BUCKETED), for c < n-1 and c < 12. Class
+ * GA_SCHED_BUCKETED), for c < n-1 and c < 15. Class
  * c runs K slots per lane and W waves per pair: classes 0-4, (K, W) = (4,1)
  * (8,1) (16,1) (24,1) (32,1), hold bands of up to 64*K diagonals; classes
  * 5, 6 and 11, (8,1) (16,1) (4,1) with a sliding window, run pairs whose
  * shorter sequence s has 2s + 11 + K <= 64K whatever the band; classes
- * 7-10, (24,2) (32,2) (32,3) (32,4), hold bands of up to
+ * 7-10, (24,2) (32,2) (32,3) (32,4), and 12-14, (8,2) (4,2) (4,4), hold
+ * bands of up to
  * 64*K + (W-1)*(64*K - 4) diagonals (3068, 4092, 6136, 8180: neighbouring
  * waves share 4 diagonals).
  * GA_EINVAL if timing was off for that call. */
 int ga_context_timing(ga_context_t *ctx, float *ms, int n);
 
-/* Class (0..11, see ga_context_timing) that ga_align_batch uses for a pair
+/* Class (0..14, see ga_context_timing) that ga_align_batch uses for a pair
  * of lengths n, m at band w: the cheapest whose kernel holds the band's
  * min(w, n) + min(w, m) + 1 diagonals (all n + m + 1 when w < 0), or, for a
  * sliding class, the pair's 2 min(n, m) + 11 + K; -1 for an empty pair or

@@ -35,7 +35,8 @@ ABI_SYMBOLS = ("ga_context_create", "ga_context_destroy", "ga_context_check", "g
                "ga_pair_class_in", "ga_context_autotune", "ga_context_pair_class", "ga_context_set_lanes",
                "ga_host_device_pointer", "ga_server_create", "ga_server_destroy", "ga_server_submit",
                "ga_server_poll", "ga_server_pending", "ga_server_batches", "ga_server_replay",
-               "ga_align_batch_noalloc", "ga_graph_capture", "ga_graph_launch", "ga_graph_destroy")
+               "ga_align_batch_noalloc", "ga_graph_capture", "ga_graph_launch", "ga_graph_destroy",
+               "ga_context_class_latency", "ga_context_set_latency_pairs", "ga_context_batch_class")
 
 GA_SCHED_PERSISTENT = 0
 GA_SCHED_BUCKETED = 1
@@ -47,7 +48,7 @@ SCHEDULES = {"persistent": GA_SCHED_PERSISTENT, "bucketed": GA_SCHED_BUCKETED, "
 # sliding one-wave class runs a short-by-long pair whose band is wider.
 CLASSES = ((4, 1, False), (8, 1, False), (16, 1, False), (24, 1, False), (32, 1, False),
            (8, 1, True), (16, 1, True), (24, 2, False), (32, 2, False), (32, 3, False), (32, 4, False),
-           (4, 1, True))
+           (4, 1, True), (8, 2, False), (4, 2, False), (4, 4, False))
 CLASS_SLOTS = tuple(k for k, _, _ in CLASSES)
 def class_capacity(c: int) -> int:
     """Diagonals class c holds: 64 K on one wave; neighbouring waves of a
@@ -129,6 +130,12 @@ def load_library() -> ctypes.CDLL:
     lib.ga_align_batch.restype = ctypes.c_int
     lib.ga_align_batch_noalloc.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), i32, i32, vp, vp]
     lib.ga_align_batch_noalloc.restype = ctypes.c_int
+    lib.ga_context_class_latency.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    lib.ga_context_class_latency.restype = ctypes.c_int
+    lib.ga_context_set_latency_pairs.argtypes = [vp, i32]
+    lib.ga_context_set_latency_pairs.restype = ctypes.c_int
+    lib.ga_context_batch_class.argtypes = [vp, i32, i32, i32, i64]
+    lib.ga_context_batch_class.restype = ctypes.c_int
     lib.ga_graph_capture.argtypes = [vp, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), i32, i32, vp, vp,
                                      ctypes.POINTER(vp)]
     lib.ga_graph_capture.restype = ctypes.c_int
@@ -258,9 +265,24 @@ class Context:
         _check(load_library().ga_context_autotune(self._h, ns, n, _stream_handle(stream)), "ga_context_autotune")
         return [float(x) for x in ns]
 
-    def pair_class(self, n: int, m: int, w: int) -> int:
-        """The class ga_align_batch on this context picks for the pair."""
-        return int(load_library().ga_context_pair_class(self._h, int(n), int(m), int(w)))
+    def pair_class(self, n: int, m: int, w: int, n_pairs: Optional[int] = None) -> int:
+        """The class ga_align_batch on this context picks for the pair (in a
+        call of ``n_pairs`` pairs: small calls may plan by latency)."""
+        if n_pairs is None:
+            return int(load_library().ga_context_pair_class(self._h, int(n), int(m), int(w)))
+        return int(load_library().ga_context_batch_class(self._h, int(n), int(m), int(w), int(n_pairs)))
+
+    def class_latency(self):
+        """The autotuner's per-class latency (ns per anti-diagonal of one pair
+        in a batch of 64)."""
+        n = len(CLASSES)
+        ns = (ctypes.c_float * n)()
+        _check(load_library().ga_context_class_latency(self._h, ns, n), "ga_context_class_latency")
+        return [float(x) for x in ns]
+
+    def set_latency_pairs(self, n_pairs: int):
+        """Calls of at most ``n_pairs`` pairs plan by latency (0: never)."""
+        _check(load_library().ga_context_set_latency_pairs(self._h, int(n_pairs)), "ga_context_set_latency_pairs")
 
     def calibrate_valu(self, stream=None) -> float:
         """Measured int32 VALU lane-ops per second of this device."""

@@ -59,14 +59,24 @@ constexpr int WAVE = 64;
 // Slot classes: K slots per lane and NW waves per pair hold the band's
 // D <= class_cap diagonals (64*K on one wave, less 4 per extra wave for the
 // shared ghost diagonals); a pair goes to the first class that holds it.
-constexpr int NCLASS = 12;
+constexpr int NCLASS = 15;
 // (K, NW, window) = (4,1,fixed) (8,1,fixed) (16,1,fixed) (24,1,fixed)
 // (32,1,fixed) (8,1,sliding) (16,1,sliding) (24,2,fixed) (32,2,fixed)
-// (32,3,fixed) (32,4,fixed) (4,1,sliding)
+// (32,3,fixed) (32,4,fixed) (4,1,sliding) (8,2,fixed) (4,2,fixed)
+// (4,4,fixed). The last three spread a band a one-wave class holds over
+// more waves: slower per pair at full occupancy (a barrier every two
+// anti-diagonals), but each wave's step is shorter, so a batch too small
+// to fill the GPU, whose time is its longest sweep, ends sooner.
 __host__ __device__ constexpr int class_k(int c) {
-    return (c == 0 || c == 11) ? 4 : (c == 1 || c == 5) ? 8 : (c == 2 || c == 6) ? 16 : (c == 3 || c == 7) ? 24 : 32;
+    return (c == 0 || c == 11 || c == 13 || c == 14) ? 4
+           : (c == 1 || c == 5 || c == 12)         ? 8
+           : (c == 2 || c == 6)                     ? 16
+           : (c == 3 || c == 7)                     ? 24
+                                                    : 32;
 }
-__host__ __device__ constexpr int class_nw(int c) { return c < 7 || c == 11 ? 1 : c < 9 ? 2 : c == 9 ? 3 : 4; }
+__host__ __device__ constexpr int class_nw(int c) {
+    return c < 7 || c == 11 ? 1 : c < 9 || c == 12 || c == 13 ? 2 : c == 9 ? 3 : 4;
+}
 __host__ __device__ constexpr bool class_slides(int c) { return c == 5 || c == 6 || c == 11; }
 // Neighbouring waves of one pair overlap by 2*HALO diagonals: each holds
 // copies ("ghosts") of the HALO diagonals next to its edge, refreshed from
@@ -97,7 +107,8 @@ constexpr uint32_t ALL_CLASSES = (1u << NCLASS) - 1;
 // classes; an autotuned context replaces it with its measured order.
 constexpr uint64_t DEFAULT_ORDER = 0x0ull | (11ull << 4) | (1ull << 8) | (5ull << 12) | (2ull << 16) |
                                    (6ull << 20) | (3ull << 24) | (4ull << 28) | (7ull << 32) |
-                                   (8ull << 36) | (9ull << 40) | (10ull << 44);
+                                   (8ull << 36) | (9ull << 40) | (10ull << 44) | (13ull << 48) |
+                                   (12ull << 52) | (14ull << 56);
 
 __host__ __device__ inline int class_for(int64_t n, int64_t m, int64_t w, int *slide,
                                          uint32_t mask = ALL_CLASSES, uint64_t order = DEFAULT_ORDER) {
@@ -1663,8 +1674,8 @@ constexpr int NEVENTS = 2 + 2 * NGROUP;
 // a full grid of another class for the resources of their wide
 // workgroups).
 constexpr int MAX_LANES = 4;
-constexpr int LANE_OF[NCLASS] = {3, 2, 3, 0, 1, 2, 3, 1, 2, 3, 3, 1};
-constexpr int LAUNCH_ORDER[NCLASS] = {10, 9, 8, 7, 0, 1, 2, 3, 4, 5, 6, 11};
+constexpr int LANE_OF[NCLASS] = {3, 2, 3, 0, 1, 2, 3, 1, 2, 3, 3, 1, 2, 1, 3};
+constexpr int LAUNCH_ORDER[NCLASS] = {10, 9, 8, 7, 14, 12, 13, 0, 1, 2, 3, 4, 5, 6, 11};
 
 struct ga_context {
     int device;
@@ -1679,6 +1690,9 @@ struct ga_context {
     uint32_t class_mask;  // kernel classes the planner may use
     uint64_t class_order; // the order the planner tries them in (autotune table)
     float class_cost[NCLASS];  // measured ns per pair and anti-diagonal (0: not tuned)
+    float class_lat[NCLASS];   // measured ns per anti-diagonal of one pair in a small batch
+    uint64_t order_lat;        // the classes by that latency, for batches of up to lat_pairs pairs
+    int lat_pairs;             // 0: no latency order (not tuned)
     int n_launch_last;              // launches of the last timed call
     int lanes;                      // streams the persistent launches spread over
     hipStream_t side[MAX_LANES - 1];
@@ -1742,7 +1756,10 @@ void launch_class(int c, const DpArgs &a, int grid, hipStream_t s) {
     case 8: launch_dp<32, 2, false>(a, grid, s); break;
     case 9: launch_dp<32, 3, false>(a, grid, s); break;
     case 10: launch_dp<32, 4, false>(a, grid, s); break;
-    default: launch_dp<4, 1, true>(a, grid, s); break;
+    case 11: launch_dp<4, 1, true>(a, grid, s); break;
+    case 12: launch_dp<8, 2, false>(a, grid, s); break;
+    case 13: launch_dp<4, 2, false>(a, grid, s); break;
+    default: launch_dp<4, 4, false>(a, grid, s); break;
     }
 }
 
@@ -1802,6 +1819,9 @@ int ga_context_create(ga_context_t **out, int device) {
     ctx->blocks_per_cu[9] = blocks_per_cu<32, 3, false>();
     ctx->blocks_per_cu[10] = blocks_per_cu<32, 4, false>();
     ctx->blocks_per_cu[11] = blocks_per_cu<4, 1, true>();
+    ctx->blocks_per_cu[12] = blocks_per_cu<8, 2, false>();
+    ctx->blocks_per_cu[13] = blocks_per_cu<4, 2, false>();
+    ctx->blocks_per_cu[14] = blocks_per_cu<4, 4, false>();
     if (hipMalloc(&ctx->d_err, sizeof(int32_t)) != hipSuccess) {
         (void)hipGetLastError();
         free(ctx);
@@ -1942,6 +1962,40 @@ static int64_t sweep_steps(int64_t n, int64_t m, int64_t w) {
     return (x < y ? x : y) + 1;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Pairs of the autotuner's latency probe (each alone on its CU).
+constexpr int LAT_PROBE = 64;
+
+// The class order a call of n_pairs pairs plans with: by measured latency
+// for a batch too small to fill the GPU (its time is its longest sweep),
+// else by throughput cost.
+uint64_t batch_order(const ga_context *ctx, int64_t n_pairs) {
+    return ctx->lat_pairs > 0 && n_pairs <= ctx->lat_pairs ? ctx->order_lat : ctx->class_order;
+}
+
+// The classes ordered by a measured cost, cheapest first (insertion sort;
+// ties keep the default order), as order nibbles.
+uint64_t order_by(const float *cost) {
+    int ord[NCLASS];
+    for (int k = 0; k < NCLASS; ++k) ord[k] = (int)((DEFAULT_ORDER >> (4 * k)) & 0xFull);
+    for (int k = 1; k < NCLASS; ++k)
+        for (int j = k; j > 0 && cost[ord[j]] < cost[ord[j - 1]]; --j) {
+            const int t = ord[j];
+            ord[j] = ord[j - 1];
+            ord[j - 1] = t;
+        }
+    uint64_t order = 0;
+    for (int k = 0; k < NCLASS; ++k) order |= (uint64_t)ord[k] << (4 * k);
+    return order;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ga_context_autotune(ga_context_t *ctx, float *ns_per_step, int n_out, void *stream) {
     if (!ctx || n_out < 0 || (n_out > 0 && !ns_per_step)) return GA_EINVAL;
     SetDevice sd(ctx->device);
@@ -1952,7 +2006,8 @@ int ga_context_autotune(ga_context_t *ctx, float *ns_per_step, int n_out, void *
     ctx->class_order = DEFAULT_ORDER;
     int rc = ga_context_set_timing(ctx, 1);
     const ga_scoring_t sc{2, 4, 4, 2, 24, 1, 1};
-    float cost[NCLASS];
+    float cost[NCLASS], lat[NCLASS];
+    ctx->lat_pairs = 0;
     for (int c = 0; c < NCLASS && rc == GA_OK; ++c) {
         // a probe each class runs in the shape the cheapest-first rule gives it
         const int K = class_k(c), cap = class_cap(c);
@@ -2003,29 +2058,53 @@ int ga_context_autotune(ga_context_t *ctx, float *ns_per_step, int n_out, void *
             rc = ga_align_batch(ctx, &bt, &sc, w, -1, (ga_result_t *)(buf + o_out), s);
         if (rc == GA_OK) rc = ga_context_timing(ctx, ms, 1 + NCLASS);
         if (rc == GA_OK) rc = ga_context_check(ctx, s);
+        const double steps = (double)sweep_steps(n, m, w);
+        cost[c] = (float)(ms[1 + c] * 1e6 / ((double)pairs * steps));
+        // latency: a batch of LAT_PROBE pairs, each alone on its CU, times
+        // one pair's sweep
+        bt.n_pairs = LAT_PROBE;
+        float ml[1 + NCLASS] = {};
+        for (int rep = 0; rep < 2 && rc == GA_OK; ++rep)
+            rc = ga_align_batch(ctx, &bt, &sc, w, -1, (ga_result_t *)(buf + o_out), s);
+        if (rc == GA_OK) rc = ga_context_timing(ctx, ml, 1 + NCLASS);
+        if (rc == GA_OK) rc = ga_context_check(ctx, s);
+        lat[c] = (float)(ml[1 + c] * 1e6 / steps);
         (void)hipFree(buf);
-        cost[c] = (float)(ms[1 + c] * 1e6 / ((double)pairs * (double)sweep_steps(n, m, w)));
     }
     ctx->class_mask = mask0;
     ctx->schedule = sched0;
     const int rc2 = ga_context_set_timing(ctx, timing0);
     if (rc == GA_OK) rc = rc2;
     if (rc != GA_OK) return rc;
-    // cheapest first (insertion sort; ties keep the default order)
-    int ord[NCLASS];
-    for (int k = 0; k < NCLASS; ++k) ord[k] = (int)((DEFAULT_ORDER >> (4 * k)) & 0xFull);
-    for (int k = 1; k < NCLASS; ++k)
-        for (int j = k; j > 0 && cost[ord[j]] < cost[ord[j - 1]]; --j) {
-            const int t = ord[j];
-            ord[j] = ord[j - 1];
-            ord[j - 1] = t;
-        }
-    uint64_t order = 0;
-    for (int k = 0; k < NCLASS; ++k) order |= (uint64_t)ord[k] << (4 * k);
-    ctx->class_order = order;
-    for (int c = 0; c < NCLASS; ++c) ctx->class_cost[c] = cost[c];
+    ctx->class_order = order_by(cost);
+    ctx->order_lat = order_by(lat);
+    ctx->lat_pairs = 2 * ctx->num_cu;
+    for (int c = 0; c < NCLASS; ++c) {
+        ctx->class_cost[c] = cost[c];
+        ctx->class_lat[c] = lat[c];
+    }
     for (int c = 0; c < n_out && c < NCLASS; ++c) ns_per_step[c] = cost[c];
     return GA_OK;
+}
+
+int ga_context_class_latency(const ga_context_t *ctx, float *ns_per_step, int n) {
+    if (!ctx || n < 0 || (n > 0 && !ns_per_step)) return GA_EINVAL;
+    if (!ctx->lat_pairs) return GA_EINVAL;
+    for (int c = 0; c < n && c < NCLASS; ++c) ns_per_step[c] = ctx->class_lat[c];
+    return GA_OK;
+}
+
+int ga_context_set_latency_pairs(ga_context_t *ctx, int32_t n_pairs) {
+    if (!ctx || n_pairs < 0) return GA_EINVAL;
+    if (!ctx->order_lat) return GA_EINVAL;  // not autotuned
+    ctx->lat_pairs = n_pairs;
+    return GA_OK;
+}
+
+int ga_context_batch_class(const ga_context_t *ctx, int32_t n, int32_t m, int32_t w, int64_t n_pairs) {
+    if (!ctx || n <= 0 || m <= 0) return -1;
+    int slide;
+    return class_for(n, m, w, &slide, ctx->class_mask, batch_order(ctx, n_pairs));
 }
 
 int ga_pair_class(int32_t n, int32_t m, int32_t w) {
@@ -2214,7 +2293,7 @@ int align_launch(ga_context *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, 
     pa.bucketed = ctx->schedule == GA_SCHED_BUCKETED ? 1 : 0;
     pa.ordered = ctx->schedule == GA_SCHED_PERSISTENT ? 1 : 0;
     pa.mask = ctx->class_mask;
-    pa.order = ctx->class_order;
+    pa.order = batch_order(ctx, np);
     pa.counters = counters;
     pa.hist = (int32_t *)(ws + WS_HIST);
     pa.cursor = (int32_t *)(ws + WS_CURSOR);
@@ -2301,8 +2380,8 @@ int align_launch(ga_context *ctx, const ga_batch_t *bt, const ga_scoring_t *sc, 
             }
         }
         int slide;
-        const int full = class_for(bt->max_len, bt->max_len, w, &slide, ctx->class_mask, ctx->class_order);
-        const uint32_t reach = reachable_classes(bt->max_len, w, ctx->class_mask, ctx->class_order);
+        const int full = class_for(bt->max_len, bt->max_len, w, &slide, ctx->class_mask, pa.order);
+        const uint32_t reach = reachable_classes(bt->max_len, w, ctx->class_mask, pa.order);
         for (int k = -1; k < NCLASS; ++k) {
             const int c = k < 0 ? full : LAUNCH_ORDER[k];
             if (c < 0 || (k >= 0 && c == full) || !((reach >> c) & 1u)) continue;

@@ -82,7 +82,7 @@ def test_pair_class_rule():
 
     import paper_2403_06478_amd as ga
     rng = np.random.default_rng(5)
-    order = [0, 11, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10]
+    order = [0, 11, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10, 13, 12, 14]
     for _ in range(3000):
         n, m = (int(x) for x in rng.integers(0, 9000, 2))
         w = int(rng.choice([-1, 0, 1, 100, 751, 1533, 1534, 2000, 2046, 3068, 4089, 4095, 5000]))
@@ -114,7 +114,7 @@ def test_pair_class_rule_restricted():
 
     import paper_2403_06478_amd as ga
     rng = np.random.default_rng(6)
-    order = [0, 11, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10]
+    order = [0, 11, 1, 5, 2, 6, 3, 4, 7, 8, 9, 10, 13, 12, 14]
     every = range(len(ga.CLASSES))
     for _ in range(3000):
         n, m = (int(x) for x in rng.integers(1, 9000, 2))

@@ -570,6 +570,9 @@ def test_every_class_same_results():
         ("w=2500", seqgen.random_pairs(rng, 4, 2700, 3000, err=0.05, w=2500, zdrop=400), [9]),
         ("w=3500", seqgen.random_pairs(rng, 3, 3600, 3800, err=0.05, w=3500, zdrop=400), [10]),
         ("sliding K4", _short_by_long(rng, 16, 1500, 2500, 20, 115, 751), [11, 5, 2, 3, 4]),
+        ("small-K waves w=400", seqgen.random_pairs(rng, 12, 900, 1100, err=0.05, w=400, zdrop=400),
+         [2, 12, 14]),
+        ("small-K waves w=200", seqgen.random_pairs(rng, 16, 500, 700, err=0.05, w=200, zdrop=300), [1, 13]),
     ]
     ctx = ga.Context(0)
     for label, b, classes in scenarios:
@@ -781,6 +784,43 @@ def test_autotune_order_and_results():
     ctx.check()
     want, _ = oracle_align(b)
     assert_same(out.cpu().numpy(), want, b, "autotuned mix sample")
+    ctx.close()
+
+
+def test_latency_order_small_batches():
+    """After autotuning, a call of few pairs plans with the classes ordered
+    by measured latency (a batch that does not fill the GPU lasts as long
+    as its longest sweep): results equal the throughput order's and the
+    oracle's, and the host's class choice for such a call is the cheapest
+    holder by the measured latencies."""
+    import torch
+
+    import paper_2403_06478_amd as ga
+    ctx = ga.Context(0)
+    cost = ctx.autotune()
+    lat = ctx.class_latency()
+    _say("latency ns/anti-diagonal: " + ", ".join(f"{ga.class_name(c)} {lat[c]:.1f}" for c in range(len(lat))))
+    assert len(lat) == len(ga.CLASSES) and all(np.isfinite(lat)) and min(lat) > 0
+    rng = np.random.default_rng(61)
+    b = seqgen.random_pairs(rng, 300, 100, 1000, err=0.05, n_rate=0.002, related=0.9, w=500, zdrop=400)
+    every = range(len(ga.CLASSES))
+    for n, m in zip(b.t_len[:60], b.q_len[:60]):
+        holders = [c for c in every if ga.ga_pair_class_in(int(n), int(m), b.w, [c]) == c]
+        got = ctx.pair_class(int(n), int(m), b.w, b.n_pairs)
+        assert got == min(holders, key=lambda c: (lat[c], holders.index(c))), (n, m, got, holders)
+    packed = ga.pack_batch(ctx, b)
+    small = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+    torch.cuda.synchronize()
+    ctx.check()
+    ctx.set_latency_pairs(0)  # the throughput order for every call
+    big = ga.ga_align_batch(ctx, packed, b.scoring, b.w, b.zdrop)
+    torch.cuda.synchronize()
+    ctx.check()
+    assert np.array_equal(small.cpu().numpy(), big.cpu().numpy())
+    want, _ = oracle_align(b)
+    assert_same(small.cpu().numpy(), want, b, "latency order")
+    used = sorted({ctx.pair_class(int(n), int(m), b.w, b.n_pairs) for n, m in zip(b.t_len, b.q_len)})
+    _say(f"latency order off: classes {used}")
     ctx.close()
 
 
