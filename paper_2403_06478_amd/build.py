@@ -16,6 +16,10 @@ HIPCC_FLAGS = [
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-value", "-Wno-unused-result",
+    # branch targets reached only by a jump start on a 32-byte boundary (the
+    # padding after an unconditional branch never executes): the sweep's
+    # per-step decisions take several such jumps
+    "-mllvm", "-align-all-nofallthru-blocks=5",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

@@ -30,12 +30,17 @@
 //
 // Bases stay 2-bit packed in HBM (plus the N bitmap). Each wave stages the
 // bases its band covers in two LDS rings (target and query), one byte per
-// base (0..3, N = 4): the ring is filled once when a pair starts and then
-// takes one word (4 bases) per sequence every 8 anti-diagonals, from a word
-// prefetched a block ahead. Per 8-step block each lane reads its byte
-// windows from the rings and each slot builds the substitution scores of its
-// next 4 cells with one v_perm_b32 table lookup (4 signed bytes); each cell
-// adds its byte through an SDWA operand.
+// base (0..3, N = 4), refilled by its lanes 64 words (256 bases) at a time
+// whenever the next block's windows reach past what a ring holds. Per 8-step
+// block each lane reads its byte windows from the rings (a block ahead) and
+// each slot builds the substitution scores of its next 4 cells with one
+// v_perm_b32 table lookup (4 signed bytes); each cell adds its byte through
+// an SDWA operand.
+//
+// The one-wave 24-slot class runs the start and end triangles of its band,
+// where an anti-diagonal's finite cells span at most 1024 diagonals, with
+// 16 slots per lane on a window placed over them, and moves the state
+// between the two slot layouts through LDS (align_pair_split).
 
 #include <hip/hip_runtime.h>
 
@@ -44,6 +49,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "ga.h"
 
@@ -90,6 +96,10 @@ __host__ __device__ constexpr int class_cap(int c) {
 constexpr int MAX_DIAGONALS = WAVE * 32 + 3 * wave_stride(32);
 
 constexpr uint32_t ALL_CLASSES = (1u << NCLASS) - 1;
+
+// Slots per lane of the start and end triangles of the one-wave 24-slot
+// class (0: the whole sweep with 24); see align_pair_split.
+constexpr int TRI_K24 = 16;
 
 // The class a pair runs in, and whether its one wave slides along the band
 // (*slide = -1 down, +1 up, 0 fixed). A band of D diagonals fits class c when
@@ -1158,9 +1168,9 @@ __device__ __forceinline__ void shift_lanes(PairState<K> &st, int *rows, int lan
     shift_array<K>(st.Y, rows, lane, dir);
 }
 
-template <int K, int NW, bool SL>
-__device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, NW> &S, int *rows) {
-    Geo g;
+// Geometry of pair p (band edges, interior diagonals, last anti-diagonal);
+// returns the band's width D in diagonals. a0w is left at a0.
+__device__ __forceinline__ int pair_geo(const DpArgs &P, int p, Geo &g) {
     g.n = P.t_len[p];
     g.m = P.q_len[p];
     const int n = g.n, m = g.m, w = P.w;
@@ -1172,63 +1182,108 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         g.a0 = -m;
         a1 = n;
     }
-    g.a0w = g.a0 + wv * wave_stride(K);
+    g.a0w = g.a0;
     g.dlo = max(g.a0, 1 - m);
     g.dhi = min(a1, n - 1);
-    const int D = a1 - g.a0 + 1;
     {
         const int dc = min(max(n - m, g.dlo), g.dhi);
         g.r_last = min(2 * n - 2 - dc, 2 * m - 2 + dc);
     }
     g.a1 = a1;
+    return a1 - g.a0 + 1;
+}
+
+// The right wall of a window whose lane 0 starts at diagonal g.a0w: the slot
+// of diagonal a1+1 if the window holds it. When the band reaches the
+// target's end (a1 = n) every cell on that diagonal lies past the target's
+// end: the exit-cell clamp of (n, -1) keeps it at -inf instead, with no
+// clamp on the other steps.
+template <int K>
+__device__ __forceinline__ void place_wall(const Geo &g, int &wall_pos, uint64_t &wall_lanes) {
+    const int Dw = g.a1 + 1 - g.a0w;
+    const bool has_wall = Dw >= 0 && Dw < WAVE * K && g.a1 < g.n;
+    wall_pos = has_wall ? Dw % K : 0;
+    wall_lanes = has_wall ? (1ull << (Dw / K)) : 0ull;
+}
+
+// The state before the first anti-diagonal, for the lane whose slots start
+// at diagonal d0: the origin (-1,-1) on anti-diagonal -2, (-1,0) and (0,-1)
+// on anti-diagonal -1 (runs of length 1), every other slot -inf; values in
+// the drifting frame.
+template <int K>
+__device__ __forceinline__ void init_state(PairState<K> &st, const DpArgs &P, const Geo &g, int d0) {
+    const int gap1 = min(P.oe1, P.oe2);
+    const int a_origin = -2 * P.e1 - P.q1;
+    const int a_ring = -gap1 - P.e1 - P.q1;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int d = d0 + s;
+        const bool held = d >= g.a0 && d <= g.a1;
+        st.A[s] = NEG;
+        st.E[s] = NEG;
+        st.X[s] = NEG;
+        st.F[s] = NEG;
+        st.Y[s] = NEG;
+        if (held && d == 0) st.A[s] = a_origin;
+        if (held && d == -1) {  // (-1,0): horizontal run of length 1
+            st.A[s] = a_ring;
+            st.F[s] = -P.oe1 - P.e1;
+            st.Y[s] = -P.oe2 - P.e2;
+        }
+        if (held && d == 1) {  // (0,-1): vertical run of length 1
+            st.A[s] = a_ring;
+            st.E[s] = -P.oe1 - P.e1;
+            st.X[s] = -P.oe2 - P.e2;
+        }
+    }
+}
+
+// One wave per pair: resolve the cell of the global maximum if its class is
+// still parked (before the park is reused, or at the end).
+template <int K>
+__device__ __forceinline__ void settle_max(Track &tr, const Geo &g, const PairLds<K, 1> &S, int lane) {
+    if (tr.g_open) {
+        int gi, gj;
+        park_cell<K, 1>(tr, g, S, lane, gi, gj);
+        tr.gi = gi;
+        tr.gj = gj;
+        tr.g_open = false;
+    }
+}
+
+// One wave per pair: the pair's result (Eq. 7's maximum and its cell, where
+// the sweep ended, whether z-drop ended it), one field per lane.
+template <int K>
+__device__ __forceinline__ void write_result(const DpArgs &P, int p, Track &tr, const Geo &g,
+                                             const PairLds<K, 1> &S, int lane) {
+    settle_max<K>(tr, g, S, lane);
+    if (lane < 7) {
+        const int G = tr.g_set ? tr.g_ma + P.q1 - P.e1 * tr.g_r : 0;
+        const int v[7] = {G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
+        int val = v[0];
+#pragma unroll
+        for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
+        reinterpret_cast<int32_t *>(P.out + p)[lane] = val;
+    }
+}
+
+template <int K, int NW, bool SL>
+__device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, NW> &S, int *rows) {
+    Geo g;
+    const int D = pair_geo(P, p, g);
+    const int n = g.n, m = g.m;
+    g.a0w = g.a0 + wv * wave_stride(K);
     // one wave on a band wider than it holds: the window slides (class_for)
     const int slide = (SL && D > WAVE * K) ? (n <= m ? -1 : 1) : 0;
     int r0 = (g.a0 & 1) ? -1 : -2;  // blocks of 8 anti-diagonals start on the class of slot 0
     if (slide < 0) g.a0w = g.a0 + K * max(0, (-r0 - 9 - g.a0) / K);
-    // the right wall: the slot of diagonal a1+1, if this wave holds it.
-    // When the band reaches the target's end (a1 = n) every cell on that
-    // diagonal lies past the target's end: the exit-cell clamp of (n, -1)
-    // keeps it at -inf instead, with no clamp on the other steps.
     int wall_pos = 0;
     uint64_t wall_lanes = 0;
-    auto place_wall = [&]() {
-        const int Dw = a1 + 1 - g.a0w;
-        const bool has_wall = Dw >= 0 && Dw < WAVE * K && a1 < n;
-        wall_pos = has_wall ? Dw % K : 0;
-        wall_lanes = has_wall ? (1ull << (Dw / K)) : 0ull;
-    };
-    place_wall();
+    place_wall<K>(g, wall_pos, wall_lanes);
 
     const int d0 = g.a0w + lane * K;
     PairState<K> st;
-    {
-        // boundary values in the frame: origin (-1,-1) on anti-diagonal -2,
-        // (-1,0) and (0,-1) on anti-diagonal -1; everything else -inf
-        const int gap1 = min(P.oe1, P.oe2);
-        const int a_origin = -2 * P.e1 - P.q1;
-        const int a_ring = -gap1 - P.e1 - P.q1;
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int d = d0 + s;
-            const bool held = d >= g.a0 && d <= a1;
-            st.A[s] = NEG;
-            st.E[s] = NEG;
-            st.X[s] = NEG;
-            st.F[s] = NEG;
-            st.Y[s] = NEG;
-            if (held && d == 0) st.A[s] = a_origin;
-            if (held && d == -1) {  // (-1,0): horizontal run of length 1
-                st.A[s] = a_ring;
-                st.F[s] = -P.oe1 - P.e1;
-                st.Y[s] = -P.oe2 - P.e2;
-            }
-            if (held && d == 1) {  // (0,-1): vertical run of length 1
-                st.A[s] = a_ring;
-                st.E[s] = -P.oe1 - P.e1;
-                st.X[s] = -P.oe2 - P.e2;
-            }
-        }
-    }
+    init_state<K>(st, P, g, d0);
     // G = 0 at the origin, in the frame of anti-diagonal -1 (the first
     // decision, for anti-diagonal 0, advances it)
     Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false, -P.q1 - P.e1};
@@ -1253,7 +1308,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
             const int lanes = (base_next - g.a0w) * dir / K;  // whole lanes by construction
             for (int k = 0; k < lanes && k < WAVE; ++k) shift_lanes<K>(st, rows, lane, dir);
             g.a0w = base_next;
-            place_wall();
+            place_wall<K>(g, wall_pos, wall_lanes);
         }
         build_scores<K>(st, wd, P);
         base_next = slide != 0 ? window_base<K>(g, slide, g.a0w, r0 + 8) : g.a0w;
@@ -1267,22 +1322,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
         if (done) break;
         r0 += 8;
     }
-    if constexpr (NW == 1) {
-        if (tr.g_open) {
-            int gi, gj;
-            park_cell<K, 1>(tr, g, S, lane, gi, gj);
-            tr.gi = gi;
-            tr.gj = gj;
-        }
-        if (lane < 7) {
-            const int G = tr.g_set ? tr.g_ma + P.q1 - P.e1 * tr.g_r : 0;
-            const int v[7] = {G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
-            int val = v[0];
-#pragma unroll
-            for (int k = 1; k < 7; ++k) val = (lane == k) ? v[k] : val;
-            reinterpret_cast<int32_t *>(P.out + p)[lane] = val;
-        }
-    }
+    if constexpr (NW == 1) write_result<K>(P, p, tr, g, S, lane);
     // (several waves: the wave that ended the sweep has written the result)
 }
 
@@ -1290,6 +1330,188 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
 // K=32 kernel needs more than the 256 registers two waves per SIMD leave it:
 // at one wave per SIMD its excess lives in accumulation registers instead of
 // scratch memory.
+// ---------------------------------------------------------------------------
+// Narrow start and end triangles. A band of D diagonals needs K slots per
+// lane only while an anti-diagonal's finite cells span more than a narrower
+// class holds. Near the origin those cells lie between the boundary cells
+// (-1, r+1) and (r+1, -1), 2r+5 diagonals; near the end, between the cells
+// leaving the rectangle. A one-wave pair of the wide class KB therefore runs
+// its first and last anti-diagonals with KT < KB slots per lane on a window
+// of 64*KT diagonals placed over them, and the middle with KB slots over the
+// whole band. The cells and decisions are those of the wide sweep: every
+// slot outside the narrow window holds -inf in the wide sweep at those
+// anti-diagonals (before row/column -1, outside the band, or past a cell
+// that left the rectangle), and the window's edge lanes see -inf beyond it.
+// The state moves between the two slot layouts through LDS, between blocks.
+
+// LDS of a pair that changes layout: the views of both layouts share the
+// storage (each phase stages its own rings), and the move between layouts
+// goes through the wide layout's park, indexed by diagonal - a0.
+template <int KB, int KT>
+union SplitLds {
+    PairLds<KB, 1> wide;
+    PairLds<KT, 1> narrow;
+};
+
+// Copy one state array from layout KF (lane 0 at diagonal a0 + f_off) to
+// layout KD (lane 0 at a0 + d_off) through `stage` (64*max(KF, KD) words,
+// word x = diagonal a0 + x); destination slots the source does not hold
+// start at -inf. Both windows lie inside [a0, a0 + 64*max(KF, KD)).
+template <int KF, int KD>
+__device__ __forceinline__ void move_array(const typename PairState<KF>::VecK &from,
+                                           typename PairState<KD>::VecK &to, int *stage, int f_off, int d_off,
+                                           int lane) {
+    int *dst = stage + d_off + lane * KD;  // even offset: 8-byte aligned pairs
+    if constexpr (KD > KF) {
+#pragma unroll
+        for (int q = 0; q < KD / 2; ++q) reinterpret_cast<int2 *>(dst)[q] = make_int2(NEG, NEG);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    int *src = stage + f_off + lane * KF;
+#pragma unroll
+    for (int q = 0; q < KF / 2; ++q) reinterpret_cast<int2 *>(src)[q] = make_int2(from[2 * q], from[2 * q + 1]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // every source slot is staged before any lane reads
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int q = 0; q < KD / 2; ++q) {
+        const int2 v = reinterpret_cast<const int2 *>(dst)[q];
+        to[2 * q] = v.x;
+        to[2 * q + 1] = v.y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // every lane has read before the next array is staged
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int KF, int KD>
+__device__ __forceinline__ void move_state(const PairState<KF> &from, PairState<KD> &to, int *stage, int f_off,
+                                           int d_off, int lane) {
+    // the stage reuses the park and the rings: their last reads come first
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    move_array<KF, KD>(from.A, to.A, stage, f_off, d_off, lane);
+    move_array<KF, KD>(from.E, to.E, stage, f_off, d_off, lane);
+    move_array<KF, KD>(from.X, to.X, stage, f_off, d_off, lane);
+    move_array<KF, KD>(from.F, to.F, stage, f_off, d_off, lane);
+    move_array<KF, KD>(from.Y, to.Y, stage, f_off, d_off, lane);
+}
+
+// One wave sweeps blocks of 8 anti-diagonals from r0 with K slots per lane,
+// lane 0 at diagonal `base`, up to the block starting at r_stop. Returns
+// true when the pair has ended (last anti-diagonal or z-drop); else false
+// with r0 = r_stop. The rings are staged afresh for this layout. (The stop
+// is worked out before the sweep: one scalar is all the loop carries beyond
+// the one-layout sweep's state.)
+template <int K>
+__device__ __forceinline__ bool sweep_window(PairState<K> &st, const DpArgs &P, Geo &g, Track &tr, int &r0,
+                                             int base, int lane, PairLds<K, 1> &S, int p, int r_stop) {
+    g.a0w = base;
+    int wall_pos = 0;
+    uint64_t wall_lanes = 0;
+    place_wall<K>(g, wall_pos, wall_lanes);
+    uint32_t *ring_t = S.ring[0][0], *ring_q = S.ring[0][1];
+    if (lane == 0) {
+        const int64_t to = P.t_off[p], qo = P.q_off[p];
+        S.src[0][0] = SeqSource{P.tw + to, P.tn, 16 * to, g.n};
+        S.src[0][1] = SeqSource{P.qw + qo, P.qn, 16 * qo, g.m};
+    }
+    __builtin_amdgcn_wave_barrier();
+    int ft = -(1 << 30), fq = -(1 << 30);
+    stage_block<K>(g, ring_t, ring_q, S.src[0], ft, fq, r0, base, lane);
+    Windows<K> wd;
+    load_windows<K>(wd, ring_t, ring_q, r0, base + lane * K);
+    for (;;) {
+        build_scores<K>(st, wd, P);
+        stage_block<K>(g, ring_t, ring_q, S.src[0], ft, fq, r0 + 8, base, lane);
+        load_windows<K>(wd, ring_t, ring_q, r0 + 8, base + lane * K);  // next block, in flight
+        if (run_block1<K>(st, P, g, tr, r0, lane, wall_lanes, wall_pos, S)) return true;
+        r0 += 8;
+        if (r0 >= r_stop) return false;
+    }
+}
+
+// A pair of the one-wave class KB whose triangles run with KT slots per
+// lane. The narrow window's lane 0 sits at bs (start) or be (end), at most
+// 64*(KB-KT) above a0, so the window lies inside the wide one.
+template <int KB, int KT>
+__device__ void align_pair_split(const DpArgs &P, int p, int lane, SplitLds<KB, KT> &U) {
+    static_assert(KT < KB && KT % 2 == 0, "the narrow layout has fewer slots, whole slot pairs");
+    Geo g;
+    pair_geo(P, p, g);
+    const int a0 = g.a0, a1 = g.a1;
+    constexpr int CAP = WAVE * KT;           // diagonals of the narrow window
+    constexpr int SPAN = WAVE * (KB - KT);  // its highest start above a0
+    int *stage = U.wide.park;
+    // start window: centred on diagonal 0 (or ending at the band's top),
+    // at or above a0 and of a0's parity, like every layout's slot 0
+    int bs = min(-CAP / 2, a1 + 1 - CAP);
+    bs = min(max(bs, a0), a0 + SPAN);
+    bs -= (bs - a0) & 1;
+    // the block from anti-diagonal r fits it when the boundary cells of its
+    // last anti-diagonal (diagonals -(r+9), r+9) do, or the band edge comes
+    // first: r <= r_fit
+    constexpr int NEVER = 1 << 30;
+    const int r_fit = min(bs == a0 ? NEVER : -bs - 9, a1 <= bs + CAP - 1 ? NEVER : bs + CAP - 10);
+    // end window for the block from r: the state holds anti-diagonals r-2
+    // and r-1, whose finite cells lie in [lo, hi] and never leave it later
+    // (boundary cells while any is in the band, else the interior cells).
+    // Cells of r-1 leaving the rectangle, still to be clamped, may fall
+    // outside: they start at -inf there, as the clamp would leave them.
+    // [lo, hi] only shrinks as r grows, so once a block fits, all later do.
+    auto end_base = [&](int r, int &be) {
+        const int lo = (-r >= a0) ? a0 : max(g.dlo, r - 2 * g.m);
+        const int hi = (r <= a1) ? a1 : min(g.dhi, 2 * g.n - r);
+        be = min(lo - ((lo - a0) & 1), a0 + SPAN);
+        return hi <= be + CAP - 1;
+    };
+    // G = 0 at the origin, in the frame of anti-diagonal -1
+    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false, -P.q1 - P.e1};
+    int r0 = (a0 & 1) ? -1 : -2;
+    PairState<KB> sw;
+    if (r0 <= r_fit) {
+        PairState<KT> sn;
+        init_state<KT>(sn, P, g, bs + lane * KT);
+        const int r_stop = r0 + 8 * ((r_fit - r0) / 8 + 1);  // first block past r_fit
+        if (sweep_window<KT>(sn, P, g, tr, r0, bs, lane, U.narrow, p, r_stop)) {
+            write_result<KT>(P, p, tr, g, U.narrow, lane);
+            return;
+        }
+        settle_max<KT>(tr, g, U.narrow, lane);
+        move_state<KT, KB>(sn, sw, stage, bs - a0, 0, lane);
+    } else {
+        init_state<KB>(sw, P, g, a0 + lane * KB);
+    }
+    int be = a0;
+    if (!end_base(r0, be)) {
+        // the first block whose state fits the end window: the block from
+        // r_last + 2 holds only the last anti-diagonal's single cell, so it
+        // fits; binary search between
+        int klo = 1, khi = (g.r_last + 2 - r0 + 7) / 8;
+        int tmp;
+        while (klo < khi) {
+            const int k = (klo + khi) >> 1;
+            if (end_base(r0 + 8 * k, tmp))
+                khi = k;
+            else
+                klo = k + 1;
+        }
+        if (sweep_window<KB>(sw, P, g, tr, r0, a0, lane, U.wide, p, r0 + 8 * klo)) {
+            write_result<KB>(P, p, tr, g, U.wide, lane);
+            return;
+        }
+        settle_max<KB>(tr, g, U.wide, lane);
+        end_base(r0, be);
+    }
+    PairState<KT> se;
+    move_state<KB, KT>(sw, se, stage, 0, be - a0, lane);
+    sweep_window<KT>(se, P, g, tr, r0, be, lane, U.narrow, p, NEVER);
+    write_result<KT>(P, p, tr, g, U.narrow, lane);
+}
+
 template <int K, int NW, bool SL>
 struct Occ {
     static constexpr int value = K <= 8 ? 4 : (K <= 16 ? 3 : (K == 32 && NW == 1 ? 1 : 2));
@@ -1299,10 +1521,13 @@ struct Occ {
 // an atomic head until the group is exhausted: persistent (a grid of
 // resident workgroups over a cost-ordered list) or one workgroup per pair
 // (the bucketed schedule).
-template <int K, int NW, bool SL>
+// KT > 0: one-wave fixed class whose start and end triangles run with KT
+// slots per lane (align_pair_split).
+template <int K, int NW, bool SL, int KT>
 __global__ __launch_bounds__(WAVE * NW, (Occ<K, NW, SL>::value)) void ga_dp_kernel(DpArgs P) {
     static_assert(!SL || NW == 1, "a sliding window runs on one wave");
-    __shared__ PairLds<K, NW> S;
+    static_assert(KT == 0 || (NW == 1 && !SL), "narrow triangles on one fixed wave");
+    __shared__ std::conditional_t<(KT > 0), SplitLds<K, KT>, PairLds<K, NW>> S;
     // lane-shift staging of a sliding window: -inf rows on both sides
     __shared__ __align__(16) int rows[SL ? (WAVE + 2) * K : 4];
     const int lane = threadIdx.x & (WAVE - 1);
@@ -1328,7 +1553,10 @@ __global__ __launch_bounds__(WAVE * NW, (Occ<K, NW, SL>::value)) void ga_dp_kern
         }
         if (idx >= count) break;
         const int p = list[idx];
-        align_pair<K, NW, SL>(P, p, lane, wv, S, rows);
+        if constexpr (KT > 0)
+            align_pair_split<K, KT>(P, p, lane, S);
+        else
+            align_pair<K, NW, SL>(P, p, lane, wv, S, rows);
     }
 }
 
@@ -1738,9 +1966,9 @@ struct SetDevice {
     }
 };
 
-template <int K, int NW, bool SL>
+template <int K, int NW, bool SL, int KT = 0>
 void launch_dp(const DpArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((ga_dp_kernel<K, NW, SL>), dim3(grid), dim3(WAVE * NW), 0, s, a);
+    hipLaunchKernelGGL((ga_dp_kernel<K, NW, SL, KT>), dim3(grid), dim3(WAVE * NW), 0, s, a);
 }
 
 void launch_class(int c, const DpArgs &a, int grid, hipStream_t s) {
@@ -1748,7 +1976,7 @@ void launch_class(int c, const DpArgs &a, int grid, hipStream_t s) {
     case 0: launch_dp<4, 1, false>(a, grid, s); break;
     case 1: launch_dp<8, 1, false>(a, grid, s); break;
     case 2: launch_dp<16, 1, false>(a, grid, s); break;
-    case 3: launch_dp<24, 1, false>(a, grid, s); break;
+    case 3: launch_dp<24, 1, false, TRI_K24>(a, grid, s); break;
     case 4: launch_dp<32, 1, false>(a, grid, s); break;
     case 5: launch_dp<8, 1, true>(a, grid, s); break;
     case 6: launch_dp<16, 1, true>(a, grid, s); break;
@@ -1763,10 +1991,10 @@ void launch_class(int c, const DpArgs &a, int grid, hipStream_t s) {
     }
 }
 
-template <int K, int NW, bool SL>
+template <int K, int NW, bool SL, int KT = 0>
 int blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ga_dp_kernel<K, NW, SL>, WAVE * NW, 0) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ga_dp_kernel<K, NW, SL, KT>, WAVE * NW, 0) != hipSuccess) {
         (void)hipGetLastError();
         nb = 0;
     }
@@ -1810,7 +2038,7 @@ int ga_context_create(ga_context_t **out, int device) {
     ctx->blocks_per_cu[0] = blocks_per_cu<4, 1, false>();
     ctx->blocks_per_cu[1] = blocks_per_cu<8, 1, false>();
     ctx->blocks_per_cu[2] = blocks_per_cu<16, 1, false>();
-    ctx->blocks_per_cu[3] = blocks_per_cu<24, 1, false>();
+    ctx->blocks_per_cu[3] = blocks_per_cu<24, 1, false, TRI_K24>();
     ctx->blocks_per_cu[4] = blocks_per_cu<32, 1, false>();
     ctx->blocks_per_cu[5] = blocks_per_cu<8, 1, true>();
     ctx->blocks_per_cu[6] = blocks_per_cu<16, 1, true>();

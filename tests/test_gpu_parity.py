@@ -599,6 +599,65 @@ def test_every_class_same_results():
     ctx.close()
 
 
+def _prefix_then_random(rng, n_pairs, lo, hi, pre_lo, pre_hi):
+    """Pairs that share a prefix of U{pre_lo..pre_hi} bases and are unrelated
+    after it: the global maximum is taken early and never moves again."""
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    T, Q = [], []
+    for _ in range(n_pairs):
+        n, m = (int(x) for x in rng.integers(lo, hi + 1, 2))
+        k = int(rng.integers(pre_lo, pre_hi + 1))
+        t = acgt[rng.integers(0, 4, n)]
+        q = acgt[rng.integers(0, 4, m)]
+        q[:k] = t[:k]
+        T.append(t.tobytes())
+        Q.append(q.tobytes())
+    return T, Q
+
+
+def test_k24_narrow_triangles():
+    """The 24-slot class runs its start and end triangles with 16 slots per
+    lane and moves the state between the layouts: results match the oracle
+    when the sweep ends in each phase, when z-drop fires in each phase, when
+    the global maximum is still parked at a hand-off, on lopsided bands
+    (a0 = -m), unbanded, and right above the 16-slot capacity."""
+    import paper_2403_06478_amd as ga
+    rng = np.random.default_rng(77)
+    sc = dict(seqgen.SCORING)
+    cases = []
+    b = seqgen.random_pairs(rng, 60, 270, 2200, err=0.1, n_rate=0.002, w=751, zdrop=400)
+    cases.append(("w=751 lengths 270..2200", b))
+    b = seqgen.random_pairs(rng, 40, 400, 2500, err=0.15, related=0.6, w=751, zdrop=60)
+    cases.append(("w=751 drops", b))
+    T, Q = _prefix_then_random(rng, 24, 600, 1800, 100, 260)
+    cases.append(("prefix then random, no z-drop", seqgen.from_lists(T, Q, sc, 751, -1)))
+    cases.append(("prefix then random, Z=300", seqgen.from_lists(T, Q, sc, 751, 300)))
+    cases.append(("lopsided a0=-m, drops", _short_by_long(rng, 20, 1800, 3000, 540, 760, 751)))
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    T, Q = [], []
+    for _ in range(20):  # query = the target's first m bases, 5% substituted
+        n, m = int(rng.integers(1800, 3001)), int(rng.integers(540, 761))
+        t = acgt[rng.integers(0, 4, n)]
+        q = t[:m].copy()
+        sub = rng.random(m) < 0.05
+        q[sub] = acgt[rng.integers(0, 4, int(sub.sum()))]
+        T.append(t.tobytes())
+        Q.append(q.tobytes())
+    cases.append(("lopsided a0=-m, to the query's end", seqgen.from_lists(T, Q, sc, 751, 400)))
+    b = seqgen.random_pairs(rng, 30, 520, 760, err=0.08, w=-1, zdrop=-1)
+    cases.append(("unbanded n+m<1536", b))
+    for w in (512, 520, 600):
+        b = seqgen.random_pairs(rng, 20, 500, 1500, err=0.1, w=w, zdrop=400)
+        cases.append((f"w={w}", b))
+    for label, b in cases:
+        cls = [ga.ga_pair_class(int(b.t_len[p]), int(b.q_len[p]), b.w) for p in range(b.n_pairs)]
+        n24 = sum(c == 3 for c in cls)
+        _say(f"k24 triangles: {label}: {b.n_pairs} pairs, {n24} in the 24-slot class")
+        assert n24 >= b.n_pairs // 2, (label, n24)
+        want, _ = oracle_align(b)
+        assert_same(gpu_align(b), want, b, label)
+
+
 def test_class_mask_errors():
     """A pair that no allowed class runs is flagged and latches GA_EDEVICE;
     the other pairs are unaffected; bad masks are rejected."""
