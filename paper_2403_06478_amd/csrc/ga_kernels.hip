@@ -457,8 +457,10 @@ struct Track {
     // one wave per pair: G in the score frame of the anti-diagonal being
     // decided (advanced by e per anti-diagonal), so the decisions compare
     // frame values and never convert back to scores; G itself is
-    // g_ma + q - e * g_r
+    // g_ma + q - e * g_r (g_r = -1 and g_ma the frame value of 0 on
+    // anti-diagonal -1 while G is at the origin)
     int gf;
+    int g_res;  // one wave per pair: g_r when G's cell was last resolved
 };
 
 // LDS of one pair's workgroup: the park of the wave holding the global
@@ -638,14 +640,15 @@ __device__ __forceinline__ int lane_max(const PairState<K> &st, const Geo &g, in
 template <int K, int C>
 __device__ __forceinline__ void take_max(const PairState<K> &st, const Geo &g, Track &tr, int r, int lane,
                                          int MA, PairLds<K, 1> &S) {
-    park_class<K, C, 1>(st, S, lane);
-    tr.gf = MA;
-    tr.g_r = r;
-    tr.g_base = g.a0w;
-    tr.g_cls = C;
-    tr.g_ma = MA;
-    tr.g_open = true;
-    tr.g_set = true;
+    // selects rather than a branch around the updates (G's anti-diagonal,
+    // frame value, holding window and class move together with gf), and a
+    // branch of its own around the park
+    tr.g_r = MA > tr.gf ? r : tr.g_r;
+    tr.g_ma = MA > tr.gf ? MA : tr.g_ma;
+    tr.g_base = MA > tr.gf ? g.a0w : tr.g_base;
+    tr.g_cls = MA > tr.gf ? C : tr.g_cls;
+    if (MA > tr.gf) park_class<K, C, 1>(st, S, lane);
+    tr.gf = max(tr.gf, MA);
 }
 
 template <int K, int C>
@@ -662,12 +665,12 @@ __device__ __forceinline__ int finish_diag(const PairState<K> &st, const DpArgs 
     // G - M, in the frame of anti-diagonal r
     const int drop = tr.gf - MA;
     if (!up && P.Z >= 0 && drop > P.Z) {
-        if (tr.g_open) {
+        if (tr.g_r != tr.g_res) {
             int gi, gj;
             park_cell<K, 1>(tr, g, S, lane, gi, gj);
             tr.gi = gi;
             tr.gj = gj;
-            tr.g_open = false;
+            tr.g_res = tr.g_r;
         }
         if (mi > tr.gi && mj > tr.gj) {
             int dd = (mi - tr.gi) - (mj - tr.gj);
@@ -865,21 +868,31 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
     const uint32_t bits_w = wall_lanes != 0 ? ((wall_pos & 1) ? 0x55u : 0xAAu) & step_bits(t1, 7) : 0u;
     const uint32_t bits_ring = step_bits(t1, max(g.a1, -g.a0) - r0 - 1);
     const int ring_r0 = P.ring_b0 + P.ring_d * r0;  // boundary value's linear piece at r0
+    const uint32_t bits_c = bits_w | bits_i | bits_j;  // steps with any clamp
+    const uint32_t bits_dec = step_bits(t1, 7);        // steps with decisions to take
+    // steps still to run: anti-diagonal r >= 0 and the pair not ended. The
+    // end clears it (no return from inside the unrolled steps, which would
+    // cost every step flow bookkeeping), so the block's later steps do
+    // nothing and the block reports the end when it returns.
+    uint32_t bits_run = step_bits(-r0, 7);
+    const int Zc = P.Z >= 0 ? P.Z : 0x7fffffff;        // z-drop threshold, none when Z < 0
 #define GA_STEP1(T)                                                                        \
     {                                                                                      \
         constexpr int C = (T) & 1;                                                         \
         constexpr int CP = C ^ 1;                                                          \
         constexpr int KC = (T) >> 1;                                                       \
         const int r = r0 + (T);                                                            \
-        if (r >= 0) {                                                                      \
+        if (bits_run & (1u << (T))) {                                                      \
             const int rp = r - 1;                                                          \
-            if (bits_w & (1u << (T))) clamp_wall<K, CP>(st, wall_lanes, wall_pos);         \
-            if (bits_i & (1u << (T))) clamp_cell<K, CP, true>(st, pi0 - (T));              \
-            if (bits_j & (1u << (T))) clamp_cell<K, CP, false>(st, pj0 + (T));             \
+            if (bits_c & (1u << (T))) {                                                    \
+                if (bits_w & (1u << (T))) clamp_wall<K, CP>(st, wall_lanes, wall_pos);     \
+                if (bits_i & (1u << (T))) clamp_cell<K, CP, true>(st, pi0 - (T));          \
+                if (bits_j & (1u << (T))) clamp_cell<K, CP, false>(st, pj0 + (T));         \
+            }                                                                              \
             int lm = lane_max<K, CP, 1>(st, g, 0, 0, false);                               \
             int MA = wave_max(lm);                                                         \
             dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                       \
-            if (r >= 1) {                                                                  \
+            if (bits_dec & (1u << (T))) {                                                  \
                 int vlo = 0, vhi = 0;                                                      \
                 bool mp = false;                                                           \
                 if (__builtin_expect((bits_ring & (1u << (T))) &&                          \
@@ -891,16 +904,19 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
                     MA = wave_max(lm);                                                     \
                 }                                                                          \
                 tr.gf += P.e1;  /* G's frame value on anti-diagonal rp */                 \
-                if (MA > LIVE_MIN) {  /* the anti-diagonal has an interior cell */         \
-                    const bool up = MA > tr.gf;                                            \
-                    if (up) take_max<K, CP>(st, g, tr, rp, lane, MA, S);                   \
-                    if (__builtin_expect(rp >= g.r_last ||                                 \
-                                         (!up && P.Z >= 0 && tr.gf - MA > P.Z), 0)) {     \
-                        const int rc = finish_diag<K, CP>(st, P, g, tr, rp, lane, lm, MA, up, \
-                                                          vlo, vhi, mp, S);                \
+                /* M above G: Eq. 7's maximum moves (never for an anti-diagonal   */       \
+                /* with no interior cell: its MA is below every frame value)      */       \
+                take_max<K, CP>(st, g, tr, rp, lane, MA, S);                               \
+                /* the last anti-diagonal, or G - M above Z (then M is not above  */       \
+                /* G: Zc >= 0), as one signed test: no overflow, G - M < 2^31    */       \
+                if (__builtin_expect(max(rp - g.r_last + 1, tr.gf - MA - Zc) > 0, 0)) {   \
+                    if (MA > LIVE_MIN) {  /* the anti-diagonal has an interior cell */     \
+                        /* M above G here exactly when G moved to this anti-diagonal */    \
+                        const int rc = finish_diag<K, CP>(st, P, g, tr, rp, lane, lm, MA,  \
+                                                          tr.g_r == rp, vlo, vhi, mp, S);  \
                         if (rc) {                                                          \
                             tr.zd = rc >> 1;                                               \
-                            return true;                                                   \
+                            bits_run = 0;                                                  \
                         }                                                                  \
                     }                                                                      \
                 }                                                                          \
@@ -916,7 +932,7 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
     GA_STEP1(6)
     GA_STEP1(7)
 #undef GA_STEP1
-    return false;
+    return bits_run == 0;
 }
 
 // Several waves per pair, 8 anti-diagonals r0 .. r0+7 in four exchanges of
@@ -1242,12 +1258,12 @@ __device__ __forceinline__ void init_state(PairState<K> &st, const DpArgs &P, co
 // still parked (before the park is reused, or at the end).
 template <int K>
 __device__ __forceinline__ void settle_max(Track &tr, const Geo &g, const PairLds<K, 1> &S, int lane) {
-    if (tr.g_open) {
+    if (tr.g_r != tr.g_res) {
         int gi, gj;
         park_cell<K, 1>(tr, g, S, lane, gi, gj);
         tr.gi = gi;
         tr.gj = gj;
-        tr.g_open = false;
+        tr.g_res = tr.g_r;
     }
 }
 
@@ -1258,7 +1274,7 @@ __device__ __forceinline__ void write_result(const DpArgs &P, int p, Track &tr, 
                                              const PairLds<K, 1> &S, int lane) {
     settle_max<K>(tr, g, S, lane);
     if (lane < 7) {
-        const int G = tr.g_set ? tr.g_ma + P.q1 - P.e1 * tr.g_r : 0;
+        const int G = tr.g_ma + P.q1 - P.e1 * tr.g_r;
         const int v[7] = {G, tr.gi, tr.gj, tr.endS, tr.endI, tr.endJ, tr.zd};
         int val = v[0];
 #pragma unroll
@@ -1286,7 +1302,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     init_state<K>(st, P, g, d0);
     // G = 0 at the origin, in the frame of anti-diagonal -1 (the first
     // decision, for anti-diagonal 0, advances it)
-    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false, -P.q1 - P.e1};
+    Track tr{0, -1, -1, 0, -1, -1, 0, -1, 0, 0, -P.q1 - P.e1, false, false, -P.q1 - P.e1, -1};
 
     // this wave's base rings and their sources, filled for the first block
     uint32_t *ring_t = S.ring[wv][0], *ring_q = S.ring[wv][1];
@@ -1469,7 +1485,7 @@ __device__ void align_pair_split(const DpArgs &P, int p, int lane, SplitLds<KB, 
         return hi <= be + CAP - 1;
     };
     // G = 0 at the origin, in the frame of anti-diagonal -1
-    Track tr{0, -1, -1, 0, -1, -1, 0, 0, 0, 0, 0, false, false, -P.q1 - P.e1};
+    Track tr{0, -1, -1, 0, -1, -1, 0, -1, 0, 0, -P.q1 - P.e1, false, false, -P.q1 - P.e1, -1};
     int r0 = (a0 & 1) ? -1 : -2;
     PairState<KB> sw;
     if (r0 <= r_fit) {
