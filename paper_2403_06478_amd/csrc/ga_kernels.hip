@@ -449,9 +449,9 @@ struct Track {
     int endS, endI, endJ; // local maximum where the sweep ended
     int zd;
     // where G was taken, kept lazily: the anti-diagonal, the wave holding
-    // the cell, the slot class and the frame value; the holding wave parks
-    // that class's values in LDS until the cell is needed
-    int g_r, g_base, g_cls, g_ma;  // g_base: diagonal of lane 0's slot 0 in the holding wave
+    // the cell and the frame value; the holding wave parks that
+    // anti-diagonal's class values in LDS until the cell is needed
+    int g_r, g_base, g_ma;  // g_base: diagonal of lane 0's slot 0 in the holding wave (several waves)
     bool g_open;  // G moved since its cell was last resolved
     bool g_set;   // G has moved off the origin
     // one wave per pair: G in the score frame of the anti-diagonal being
@@ -549,7 +549,7 @@ __device__ __forceinline__ void locate(const PairState<K> &st, const Geo &g, int
 }
 
 // The cell of the global maximum, from the values its wave parked: the
-// lowest (lane, slot) of class g_cls holding g_ma on an interior diagonal of
+// lowest (lane, slot) of g_r's class holding g_ma on an interior diagonal of
 // anti-diagonal g_r. Any wave of the pair can run it once the park is
 // visible to it.
 template <int K, int NW>
@@ -557,17 +557,22 @@ __device__ __forceinline__ void park_cell(const Track &tr, const Geo &g, const P
                                           int &gi, int &gj) {
     int vlo, vhi;
     diag_window(g, tr.g_r, vlo, vhi);
-    const int dl = tr.g_base + lane * K + tr.g_cls;  // this lane's first class slot
+    // the holding window (one wave: the current one, see take_max) and the
+    // class of anti-diagonal g_r in it: slot s holds a diagonal of g_r's
+    // parity when s = g_r - base (mod 2)
+    const int gb = NW == 1 ? g.a0w : tr.g_base;
+    const int cls = (tr.g_r - gb) & 1;
+    const int dl = gb + lane * K + cls;  // this lane's first class slot
     int hit = K;
 #pragma unroll
     for (int t = K / 2 - 1; t >= 0; --t) {
-        const int v = S.park[(tr.g_cls + 2 * t) * WAVE + lane];
+        const int v = S.park[(cls + 2 * t) * WAVE + lane];
         const int d = dl + 2 * t;
         if (v == tr.g_ma && d >= vlo && d <= vhi) hit = t;
     }
     const int L = __builtin_ctzll(__ballot(hit < K));
     const int t = __builtin_amdgcn_readlane(hit, L);
-    const int dm = tr.g_base + L * K + tr.g_cls + 2 * t;
+    const int dm = gb + L * K + cls + 2 * t;
     gi = (tr.g_r + dm) >> 1;
     gj = (tr.g_r - dm) >> 1;
 }
@@ -640,23 +645,22 @@ __device__ __forceinline__ int lane_max(const PairState<K> &st, const Geo &g, in
 template <int K, int C>
 __device__ __forceinline__ void take_max(const PairState<K> &st, const Geo &g, Track &tr, int r, int lane,
                                          int MA, PairLds<K, 1> &S) {
-    // selects rather than a branch around the updates (G's anti-diagonal,
-    // frame value, holding window and class move together with gf), and a
-    // branch of its own around the park
-    tr.g_r = MA > tr.gf ? r : tr.g_r;
-    tr.g_ma = MA > tr.gf ? MA : tr.g_ma;
-    tr.g_base = MA > tr.gf ? g.a0w : tr.g_base;
-    tr.g_cls = MA > tr.gf ? C : tr.g_cls;
-    if (MA > tr.gf) park_class<K, C, 1>(st, S, lane);
+    // (G's window is the current one: a one-wave pair resolves G's cell
+    // before its window moves; its class follows from g_r)
+    if (MA > tr.gf) {
+        park_class<K, C, 1>(st, S, lane);
+        tr.g_r = r;
+        tr.g_ma = MA;
+    }
     tr.gf = max(tr.gf, MA);
 }
 
 template <int K, int C>
 __device__ __forceinline__ int finish_diag(const PairState<K> &st, const DpArgs &P, const Geo &g, Track &tr,
-                                           int r, int lane, int lm, int MA, bool up, int vlo, int vhi,
-                                           bool masked, PairLds<K, 1> &S) {
+                                           int r, int lane, int lm, int MA, bool up, PairLds<K, 1> &S) {
     const bool last = r >= g.r_last;
-    if (!masked) diag_window(g, r, vlo, vhi);
+    int vlo, vhi;
+    diag_window(g, r, vlo, vhi);
     int mi, mj;
     locate<K, C>(st, g, lm, MA, r, vlo, vhi, mi, mj);
     tr.endS = MA + P.q1 - P.e1 * r;  // back to the true score
@@ -736,7 +740,6 @@ __device__ __forceinline__ bool decide_mw(const PairState<K> &st, const DpArgs &
         tr.G = M;
         tr.g_r = r;
         tr.g_base = g.a0 + vstar * wave_stride(K);
-        tr.g_cls = C;
         tr.g_ma = MA;
         tr.g_set = true;
     }
@@ -876,6 +879,7 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
     // nothing and the block reports the end when it returns.
     uint32_t bits_run = step_bits(-r0, 7);
     const int Zc = P.Z >= 0 ? P.Z : 0x7fffffff;        // z-drop threshold, none when Z < 0
+    const int end0 = r0 - g.r_last;                    // step T decides r_last when end0 + T > 0
 #define GA_STEP1(T)                                                                        \
     {                                                                                      \
         constexpr int C = (T) & 1;                                                         \
@@ -893,12 +897,10 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
             int MA = wave_max(lm);                                                         \
             dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                       \
             if (bits_dec & (1u << (T))) {                                                  \
-                int vlo = 0, vhi = 0;                                                      \
-                bool mp = false;                                                           \
                 if (__builtin_expect((bits_ring & (1u << (T))) &&                          \
                                      MA == max(P.ring_a0, ring_r0 + P.ring_d * ((T) - 1)), 0)) { \
                     /* a boundary cell may hold the maximum: redo it masked */             \
-                    mp = true;                                                             \
+                    int vlo, vhi;                                                          \
                     diag_window(g, rp, vlo, vhi);                                          \
                     lm = lane_max<K, CP, 1>(st, g, vlo, vhi, true);                        \
                     MA = wave_max(lm);                                                     \
@@ -909,11 +911,11 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
                 take_max<K, CP>(st, g, tr, rp, lane, MA, S);                               \
                 /* the last anti-diagonal, or G - M above Z (then M is not above  */       \
                 /* G: Zc >= 0), as one signed test: no overflow, G - M < 2^31    */       \
-                if (__builtin_expect(max(rp - g.r_last + 1, tr.gf - MA - Zc) > 0, 0)) {   \
+                if (__builtin_expect(max(end0 + (T), tr.gf - MA - Zc) > 0, 0)) {           \
                     if (MA > LIVE_MIN) {  /* the anti-diagonal has an interior cell */     \
                         /* M above G here exactly when G moved to this anti-diagonal */    \
                         const int rc = finish_diag<K, CP>(st, P, g, tr, rp, lane, lm, MA,  \
-                                                          tr.g_r == rp, vlo, vhi, mp, S);  \
+                                                          tr.g_r == rp, S);                \
                         if (rc) {                                                          \
                             tr.zd = rc >> 1;                                               \
                             bits_run = 0;                                                  \
@@ -1302,7 +1304,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     init_state<K>(st, P, g, d0);
     // G = 0 at the origin, in the frame of anti-diagonal -1 (the first
     // decision, for anti-diagonal 0, advances it)
-    Track tr{0, -1, -1, 0, -1, -1, 0, -1, 0, 0, -P.q1 - P.e1, false, false, -P.q1 - P.e1, -1};
+    Track tr{0, -1, -1, 0, -1, -1, 0, -1, 0, -P.q1 - P.e1, false, false, -P.q1 - P.e1, -1};
 
     // this wave's base rings and their sources, filled for the first block
     uint32_t *ring_t = S.ring[wv][0], *ring_q = S.ring[wv][1];
@@ -1319,6 +1321,7 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     int base_next = g.a0w;
     for (;;) {
         if (slide != 0 && base_next != g.a0w) {
+            if constexpr (NW == 1) settle_max<K>(tr, g, S, lane);  // G's cell, while its window is current
             // move the window to this block's base, one lane at a time
             const int dir = base_next < g.a0w ? -1 : 1;
             const int lanes = (base_next - g.a0w) * dir / K;  // whole lanes by construction
@@ -1485,7 +1488,7 @@ __device__ void align_pair_split(const DpArgs &P, int p, int lane, SplitLds<KB, 
         return hi <= be + CAP - 1;
     };
     // G = 0 at the origin, in the frame of anti-diagonal -1
-    Track tr{0, -1, -1, 0, -1, -1, 0, -1, 0, 0, -P.q1 - P.e1, false, false, -P.q1 - P.e1, -1};
+    Track tr{0, -1, -1, 0, -1, -1, 0, -1, 0, -P.q1 - P.e1, false, false, -P.q1 - P.e1, -1};
     int r0 = (a0 & 1) ? -1 : -2;
     PairState<KB> sw;
     if (r0 <= r_fit) {
