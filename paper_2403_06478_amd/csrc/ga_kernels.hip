@@ -300,6 +300,12 @@ struct PairState {
     typedef int VecK __attribute__((ext_vector_type(K)));
     VecK A, E, X, F, Y;
     uint32_t S4[K];  // s' of the slot's next 4 cells, one signed byte each
+    // the lane-edge neighbours: A, E, X of the lower lane's slot K-1 and
+    // A, F, Y of the upper lane's slot 0, received by DPP each step into
+    // the same registers. Lane 0 of the first three and lane 63 of the
+    // others have no neighbour and keep -inf from the pair's start: a DPP
+    // move leaves such a lane's old value, so no fill precedes it.
+    int eA, eE, eX, fA, fF, fY;
 };
 
 // One slot update (class C slot S, block cell KC). Inputs come from the
@@ -341,22 +347,22 @@ __device__ __forceinline__ void update_class(PairState<K> &st, const DpArgs &P, 
 }
 
 // Update the slots of parity class C with cell index KC (0..3) of the block.
-// f0..f2 enter at the pair's outer lane edge: lane 0's lower neighbour (A, E,
-// X) for class 0, lane 63's upper neighbour (A, F, Y) for class 1. They are
-// -inf at a band edge and the neighbouring wave's edge values inside a
-// multi-wave pair.
+// Beyond the wave's outer lanes (lane 0's lower neighbour for class 0,
+// lane 63's upper one for class 1) the values are -inf: the band edge, or
+// in a multi-wave pair the next wave's edge, which the ghost diagonals
+// stand in for.
 template <int K, int C, int KC>
-__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P, int f0, int f1, int f2) {
+__device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P) {
     int ae = 0, ee = 0, xe = 0;  // class 0: slot -1 = lower lane's slot K-1 (up)
     int af = 0, ff = 0, yf = 0;  // class 1: slot K = upper lane's slot 0 (left)
     if (C == 0) {
-        ae = dpp_from_lower_lane(f0, st.A[K - 1]);
-        ee = dpp_from_lower_lane(f1, st.E[K - 1]);
-        xe = dpp_from_lower_lane(f2, st.X[K - 1]);
+        ae = st.eA = dpp_from_lower_lane(st.eA, st.A[K - 1]);
+        ee = st.eE = dpp_from_lower_lane(st.eE, st.E[K - 1]);
+        xe = st.eX = dpp_from_lower_lane(st.eX, st.X[K - 1]);
     } else {
-        af = dpp_from_upper_lane(f0, st.A[0]);
-        ff = dpp_from_upper_lane(f1, st.F[0]);
-        yf = dpp_from_upper_lane(f2, st.Y[0]);
+        af = st.fA = dpp_from_upper_lane(st.fA, st.A[0]);
+        ff = st.fF = dpp_from_upper_lane(st.fF, st.F[0]);
+        yf = st.fY = dpp_from_upper_lane(st.fY, st.Y[0]);
     }
     // piece-2 openings of the other class, shared by both neighbours
     int B[K];
@@ -895,7 +901,7 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
             }                                                                              \
             int lm = lane_max<K, CP, 1>(st, g, 0, 0, false);                               \
             int MA = wave_max(lm);                                                         \
-            dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                       \
+            dp_step<K, C, KC>(st, P);                                       \
             if (bits_dec & (1u << (T))) {                                                  \
                 if (__builtin_expect((bits_ring & (1u << (T))) &&                          \
                                      MA == max(P.ring_a0, ring_r0 + P.ring_d * ((T) - 1)), 0)) { \
@@ -967,7 +973,7 @@ __device__ __forceinline__ bool run_block(PairState<K> &st, const DpArgs &P, con
         constexpr int C = (T) & 1;                                                    \
         constexpr int KC = (T) >> 1;                                                  \
         if (r0 + (T) >= 0) {                                                          \
-            dp_step<K, C, KC>(st, P, NEG, NEG, NEG);                                  \
+            dp_step<K, C, KC>(st, P);                                  \
             if (bits_w & (1u << (T))) clamp_wall<K, C>(st, wall_lanes, wall_pos);     \
             if (bits_i & (1u << (T))) clamp_cell<K, C, true>(st, pi0 - (T));          \
             if (bits_j & (1u << (T))) clamp_cell<K, C, false>(st, pj0 + (T));         \
@@ -1233,6 +1239,7 @@ __device__ __forceinline__ void init_state(PairState<K> &st, const DpArgs &P, co
     const int gap1 = min(P.oe1, P.oe2);
     const int a_origin = -2 * P.e1 - P.q1;
     const int a_ring = -gap1 - P.e1 - P.q1;
+    st.eA = st.eE = st.eX = st.fA = st.fF = st.fY = NEG;
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         const int d = d0 + s;
@@ -1417,6 +1424,7 @@ __device__ __forceinline__ void move_state(const PairState<KF> &from, PairState<
     move_array<KF, KD>(from.X, to.X, stage, f_off, d_off, lane);
     move_array<KF, KD>(from.F, to.F, stage, f_off, d_off, lane);
     move_array<KF, KD>(from.Y, to.Y, stage, f_off, d_off, lane);
+    to.eA = to.eE = to.eX = to.fA = to.fF = to.fY = NEG;
 }
 
 // One wave sweeps blocks of 8 anti-diagonals from r0 with K slots per lane,
