@@ -97,9 +97,11 @@ constexpr int MAX_DIAGONALS = WAVE * 32 + 3 * wave_stride(32);
 
 constexpr uint32_t ALL_CLASSES = (1u << NCLASS) - 1;
 
-// Slots per lane of the start and end triangles of the one-wave 24-slot
-// class (0: the whole sweep with 24); see align_pair_split.
+// Slots per lane of the start and end triangles of the one-wave 24- and
+// 16-slot classes (0: the whole sweep with one layout); see
+// align_pair_split.
 constexpr int TRI_K24 = 16;
+constexpr int TRI_K16 = 8;
 
 // The class a pair runs in, and whether its one wave slides along the band
 // (*slide = -1 down, +1 up, 0 fixed). A band of D diagonals fits class c when
@@ -2002,7 +2004,7 @@ void launch_class(int c, const DpArgs &a, int grid, hipStream_t s) {
     switch (c) {
     case 0: launch_dp<4, 1, false>(a, grid, s); break;
     case 1: launch_dp<8, 1, false>(a, grid, s); break;
-    case 2: launch_dp<16, 1, false>(a, grid, s); break;
+    case 2: launch_dp<16, 1, false, TRI_K16>(a, grid, s); break;
     case 3: launch_dp<24, 1, false, TRI_K24>(a, grid, s); break;
     case 4: launch_dp<32, 1, false>(a, grid, s); break;
     case 5: launch_dp<8, 1, true>(a, grid, s); break;
@@ -2064,7 +2066,7 @@ int ga_context_create(ga_context_t **out, int device) {
     // persistent grids: as many workgroups as the registers let reside
     ctx->blocks_per_cu[0] = blocks_per_cu<4, 1, false>();
     ctx->blocks_per_cu[1] = blocks_per_cu<8, 1, false>();
-    ctx->blocks_per_cu[2] = blocks_per_cu<16, 1, false>();
+    ctx->blocks_per_cu[2] = blocks_per_cu<16, 1, false, TRI_K16>();
     ctx->blocks_per_cu[3] = blocks_per_cu<24, 1, false, TRI_K24>();
     ctx->blocks_per_cu[4] = blocks_per_cu<32, 1, false>();
     ctx->blocks_per_cu[5] = blocks_per_cu<8, 1, true>();

@@ -658,6 +658,46 @@ def test_k24_narrow_triangles():
         assert_same(gpu_align(b), want, b, label)
 
 
+def test_k16_narrow_triangles():
+    """The 16-slot class runs its start and end triangles with 8 slots per
+    lane: the same hand-offs as the 24-slot class's, on bands of 513-1024
+    diagonals (short pairs inside a wide band, whose whole sweep is start
+    and end triangle, long pairs in a narrow band, lopsided, unbanded,
+    drops, a parked maximum at a hand-off)."""
+    import paper_2403_06478_amd as ga
+    rng = np.random.default_rng(78)
+    sc = dict(seqgen.SCORING)
+    cases = []
+    cases.append(("w=751 lengths 260..510", seqgen.random_pairs(rng, 60, 260, 510, err=0.1, n_rate=0.002,
+                                                                  w=751, zdrop=400)))
+    cases.append(("w=751 drops", seqgen.random_pairs(rng, 40, 270, 500, err=0.15, related=0.6, w=751,
+                                                      zdrop=40)))
+    for w in (257, 300, 400, 511):
+        cases.append((f"w={w}", seqgen.random_pairs(rng, 20, 600, 1600, err=0.1, w=w, zdrop=400)))
+    T, Q = _prefix_then_random(rng, 24, 600, 1400, 60, 180)
+    cases.append(("prefix then random, no z-drop", seqgen.from_lists(T, Q, sc, 400, -1)))
+    cases.append(("prefix then random, Z=200", seqgen.from_lists(T, Q, sc, 400, 200)))
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    T, Q = [], []
+    for _ in range(20):  # query = the target's first m bases, 5% substituted
+        n, m = int(rng.integers(1000, 2001)), int(rng.integers(260, 381))
+        t = acgt[rng.integers(0, 4, n)]
+        q = t[:m].copy()
+        sub = rng.random(m) < 0.05
+        q[sub] = acgt[rng.integers(0, 4, int(sub.sum()))]
+        T.append(t.tobytes())
+        Q.append(q.tobytes())
+    cases.append(("lopsided a0=-m", seqgen.from_lists(T, Q, sc, 400, 400)))
+    cases.append(("unbanded n+m<1024", seqgen.random_pairs(rng, 30, 270, 500, err=0.08, w=-1, zdrop=-1)))
+    for label, b in cases:
+        cls = [ga.ga_pair_class(int(b.t_len[p]), int(b.q_len[p]), b.w) for p in range(b.n_pairs)]
+        n16 = sum(c == 2 for c in cls)
+        _say(f"k16 triangles: {label}: {b.n_pairs} pairs, {n16} in the 16-slot class")
+        assert n16 >= b.n_pairs // 2, (label, n16)
+        want, _ = oracle_align(b)
+        assert_same(gpu_align(b), want, b, label)
+
+
 def test_class_mask_errors():
     """A pair that no allowed class runs is flagged and latches GA_EDEVICE;
     the other pairs are unaffected; bad masks are rejected."""
