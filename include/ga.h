@@ -280,7 +280,9 @@ int ga_context_set_timing(ga_context_t *ctx, int enable);
  * 7-10, (24,2) (32,2) (32,3) (32,4), and 12-14, (8,2) (4,2) (4,4), hold
  * bands of up to
  * 64*K + (W-1)*(64*K - 4) diagonals (3068, 4092, 6136, 8180: neighbouring
- * waves share 4 diagonals).
+ * waves share 4 diagonals). Classes 3 and 2 run the start and end
+ * triangles of a band (while an anti-diagonal's finite cells fit) with 16
+ * and 8 slots per lane inside the same launch.
  * GA_EINVAL if timing was off for that call. */
 int ga_context_timing(ga_context_t *ctx, float *ms, int n);
 
