@@ -353,11 +353,23 @@ __device__ __forceinline__ void update_class(PairState<K> &st, const DpArgs &P, 
 // lane 63's upper one for class 1) the values are -inf: the band edge, or
 // in a multi-wave pair the next wave's edge, which the ghost diagonals
 // stand in for.
-template <int K, int C, int KC>
+template <int K, int C, int KC, bool EDGE_REGS = true>
 __device__ __forceinline__ void dp_step(PairState<K> &st, const DpArgs &P) {
     int ae = 0, ee = 0, xe = 0;  // class 0: slot -1 = lower lane's slot K-1 (up)
     int af = 0, ff = 0, yf = 0;  // class 1: slot K = upper lane's slot 0 (left)
-    if (C == 0) {
+    if constexpr (!EDGE_REGS) {
+        // (one wave of 32 slots: no registers to spare for the six edge
+        // registers; a -inf fill per move instead)
+        if (C == 0) {
+            ae = dpp_from_lower_lane(NEG, st.A[K - 1]);
+            ee = dpp_from_lower_lane(NEG, st.E[K - 1]);
+            xe = dpp_from_lower_lane(NEG, st.X[K - 1]);
+        } else {
+            af = dpp_from_upper_lane(NEG, st.A[0]);
+            ff = dpp_from_upper_lane(NEG, st.F[0]);
+            yf = dpp_from_upper_lane(NEG, st.Y[0]);
+        }
+    } else if (C == 0) {
         ae = st.eA = dpp_from_lower_lane(st.eA, st.A[K - 1]);
         ee = st.eE = dpp_from_lower_lane(st.eE, st.E[K - 1]);
         xe = st.eX = dpp_from_lower_lane(st.eX, st.X[K - 1]);
@@ -903,7 +915,7 @@ __device__ __forceinline__ bool run_block1(PairState<K> &st, const DpArgs &P, co
             }                                                                              \
             int lm = lane_max<K, CP, 1>(st, g, 0, 0, false);                               \
             int MA = wave_max(lm);                                                         \
-            dp_step<K, C, KC>(st, P);                                       \
+            dp_step<K, C, KC, (K < 32)>(st, P);                                            \
             if (bits_dec & (1u << (T))) {                                                  \
                 if (__builtin_expect((bits_ring & (1u << (T))) &&                          \
                                      MA == max(P.ring_a0, ring_r0 + P.ring_d * ((T) - 1)), 0)) { \
