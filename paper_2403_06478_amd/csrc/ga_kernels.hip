@@ -1164,25 +1164,27 @@ __device__ __forceinline__ int window_base(const Geo &g, int slide, int base, in
     return base;
 }
 
-// Move the window one lane: down (dir < 0: lane l takes lane l-1's slots,
-// lane 0 starts at -inf) or up (lane l takes lane l+1's, lane 63 at -inf).
-// Each state array goes through LDS: row l+1 of `rows` takes lane l's K
-// slots, then every lane reads the row of its neighbour; rows 0 and 65 hold
-// -inf for the lane with no neighbour on that side. Staging costs no
-// registers beyond the state, and the rows are reused array after array.
+// Move the window by `step` lanes (-2, -1, 1 or 2): down (step < 0: lane l
+// takes lane l+step's slots, the lowest lanes start at -inf) or up (lane l
+// takes lane l+step's, the highest lanes at -inf). Each state array goes
+// through LDS: row l+2 of `rows` takes lane l's K slots, then every lane
+// reads the row `step` away; rows 0, 1 and 66, 67 hold -inf for the lanes
+// with no source on that side. Staging costs no registers beyond the
+// state, and the rows are reused array after array; a two-lane move (a
+// 4-slot window moves two lanes per block) costs one round trip.
 // A sliding window's workgroup is one wave, whose LDS operations complete
 // in order: a wave-level scheduling barrier keeps the compiler from moving
 // the reads above the writes (or the next array's writes above the reads),
 // and no workgroup barrier is needed.
 template <int K>
-__device__ __forceinline__ void shift_array(typename PairState<K>::VecK &a, int *rows, int lane, int dir) {
-    int4 *own = reinterpret_cast<int4 *>(rows + (lane + 1) * K);
+__device__ __forceinline__ void shift_array(typename PairState<K>::VecK &a, int *rows, int lane, int step) {
+    int4 *own = reinterpret_cast<int4 *>(rows + (lane + 2) * K);
 #pragma unroll
     for (int q = 0; q < K / 4; ++q) own[q] = make_int4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();  // every row is staged before any lane reads its neighbour's
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int4 *from = reinterpret_cast<const int4 *>(rows + (lane + 1 + dir) * K);
+    const int4 *from = reinterpret_cast<const int4 *>(rows + (lane + 2 + step) * K);
 #pragma unroll
     for (int q = 0; q < K / 4; ++q) {
         const int4 v = from[q];
@@ -1197,13 +1199,13 @@ __device__ __forceinline__ void shift_array(typename PairState<K>::VecK &a, int 
 }
 
 template <int K>
-__device__ __forceinline__ void shift_lanes(PairState<K> &st, int *rows, int lane, int dir) {
+__device__ __forceinline__ void shift_lanes(PairState<K> &st, int *rows, int lane, int step) {
     static_assert(K % 4 == 0, "rows are staged 16 bytes at a time");
-    shift_array<K>(st.A, rows, lane, dir);
-    shift_array<K>(st.E, rows, lane, dir);
-    shift_array<K>(st.X, rows, lane, dir);
-    shift_array<K>(st.F, rows, lane, dir);
-    shift_array<K>(st.Y, rows, lane, dir);
+    shift_array<K>(st.A, rows, lane, step);
+    shift_array<K>(st.E, rows, lane, step);
+    shift_array<K>(st.X, rows, lane, step);
+    shift_array<K>(st.F, rows, lane, step);
+    shift_array<K>(st.Y, rows, lane, step);
 }
 
 // Geometry of pair p (band edges, interior diagonals, last anti-diagonal);
@@ -1343,10 +1345,14 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     for (;;) {
         if (slide != 0 && base_next != g.a0w) {
             if constexpr (NW == 1) settle_max<K>(tr, g, S, lane);  // G's cell, while its window is current
-            // move the window to this block's base, one lane at a time
+            // move the window to this block's base, two lanes at a time
             const int dir = base_next < g.a0w ? -1 : 1;
-            const int lanes = (base_next - g.a0w) * dir / K;  // whole lanes by construction
-            for (int k = 0; k < lanes && k < WAVE; ++k) shift_lanes<K>(st, rows, lane, dir);
+            int lanes = min((base_next - g.a0w) * dir / K, WAVE);  // whole lanes by construction
+            while (lanes > 0) {
+                const int k = lanes >= 2 ? 2 : 1;
+                shift_lanes<K>(st, rows, lane, dir * k);
+                lanes -= k;
+            }
             g.a0w = base_next;
             place_wall<K>(g, wall_pos, wall_lanes);
         }
@@ -1569,13 +1575,13 @@ __global__ __launch_bounds__(WAVE * NW, (Occ<K, NW, SL>::value)) void ga_dp_kern
     static_assert(!SL || NW == 1, "a sliding window runs on one wave");
     static_assert(KT == 0 || (NW == 1 && !SL), "narrow triangles on one fixed wave");
     __shared__ std::conditional_t<(KT > 0), SplitLds<K, KT>, PairLds<K, NW>> S;
-    // lane-shift staging of a sliding window: -inf rows on both sides
-    __shared__ __align__(16) int rows[SL ? (WAVE + 2) * K : 4];
+    // lane-shift staging of a sliding window: two -inf rows on each side
+    __shared__ __align__(16) int rows[SL ? (WAVE + 4) * K : 4];
     const int lane = threadIdx.x & (WAVE - 1);
     if constexpr (SL) {
-        if (lane < K) {
+        if (lane < 2 * K) {
             rows[lane] = NEG;
-            rows[(WAVE + 1) * K + lane] = NEG;
+            rows[(WAVE + 2) * K + lane] = NEG;
         }
     }
     const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
