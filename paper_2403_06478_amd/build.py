@@ -20,6 +20,10 @@ HIPCC_FLAGS = [
     # padding after an unconditional branch never executes): the sweep's
     # per-step decisions take several such jumps
     "-mllvm", "-align-all-nofallthru-blocks=5",
+    # the iterative ILP machine scheduler: same occupancy for every kernel,
+    # and the one-wave 32-slot sweep fits two waves per SIMD (252 VGPRs
+    # against 302 with accumulation-register traffic under the default)
+    "-mllvm", "-amdgpu-sched-strategy=iterative-ilp",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

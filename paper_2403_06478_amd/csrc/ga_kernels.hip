@@ -1372,10 +1372,6 @@ __device__ void align_pair(const DpArgs &P, int p, int lane, int wv, PairLds<K, 
     // (several waves: the wave that ended the sweep has written the result)
 }
 
-// Waves per SIMD each kernel is compiled for (register budget). The one-wave
-// K=32 kernel needs more than the 256 registers two waves per SIMD leave it:
-// at one wave per SIMD its excess lives in accumulation registers instead of
-// scratch memory.
 // ---------------------------------------------------------------------------
 // Narrow start and end triangles. A band of D diagonals needs K slots per
 // lane only while an anti-diagonal's finite cells span more than a narrower
@@ -1559,9 +1555,14 @@ __device__ void align_pair_split(const DpArgs &P, int p, int lane, SplitLds<KB, 
     write_result<KT>(P, p, tr, g, U.narrow, lane);
 }
 
+// Waves per SIMD each kernel is compiled for (its register budget: 512 per
+// SIMD lane over the resident waves). The one-wave K=32 kernel fits two
+// waves in 256 registers only with the iterative ILP scheduler the library
+// is built with (252); the default one left it at one wave per SIMD, its
+// excess in accumulation registers.
 template <int K, int NW, bool SL>
 struct Occ {
-    static constexpr int value = K <= 8 ? 4 : (K <= 16 ? 3 : (K == 32 && NW == 1 ? 1 : 2));
+    static constexpr int value = K <= 8 ? 4 : (K <= 16 ? 3 : 2);
 };
 
 // Each workgroup of NW waves takes pairs of its group from the list through
